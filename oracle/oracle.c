@@ -1,0 +1,185 @@
+/*
+ * oracle.c -- plain CPU reference for the single-linkage dendrogram of a
+ * minimum spanning tree.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file: only the tests, the smoke check and the benchmark's CPU
+ * baseline use it.  It shares no code, header, table or helper with the GPU
+ * library; the only thing the two sides have in common is the meaning of the
+ * inputs and outputs.
+ *
+ * What it computes (paper, Section 2.3.2, bottom-up construction): visit the
+ * MST edges from lightest to heaviest; each edge merges the two clusters that
+ * contain its endpoints, and becomes the parent of the two nodes that
+ * currently stand for those clusters (a vertex if the cluster is still a
+ * single vertex, otherwise the edge that last merged it).  A union-find
+ * structure (Tarjan) tracks cluster membership.
+ *
+ * Readings of the paper fixed here:
+ *   - Order.  Section 3.1.1 asks for a consistent order on equal weights so
+ *     that the dendrogram is unique.  We use the lexicographic order of
+ *     (w, edge id), ascending: among equal weights the lower input id is the
+ *     lighter edge.  Weights are compared by IEEE value, so -0.0 and +0.0
+ *     tie and fall to the id; +-inf are ordinary values; NaN is rejected.
+ *   - Numbering.  Every output names INPUT edge ids.  The root edge has
+ *     parent -1; for a one-vertex tree vertex_parent[0] = -1.
+ *   - Vertex parent.  The first edge in this order that touches a vertex
+ *     (its lightest incident edge).  This is the paper's Eq. (vertexparent),
+ *     whose "largest index" is the lightest edge because the paper indexes
+ *     edges by descending weight.
+ *   - Non-tree input (a repeated component while merging) is an error.
+ *
+ * Status codes (numeric values are part of the documented interface):
+ *   0 ok, 1 invalid argument, 2 not a tree, 3 NaN weight, 6 vertex id out of
+ *   range.  Checks run in the order: arguments, vertex ids, NaN, tree.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+enum {
+    ORC_OK = 0,
+    ORC_INVALID_ARG = 1,
+    ORC_NOT_A_TREE = 2,
+    ORC_NAN_WEIGHT = 3,
+    ORC_BAD_VERTEX = 6,
+};
+
+typedef struct {
+    float w;
+    int32_t id;
+} orc_edge_key;
+
+/* Strict total order on (w, id): the order the whole method is defined on. */
+static int orc_cmp(const void* pa, const void* pb)
+{
+    const orc_edge_key* a = (const orc_edge_key*)pa;
+    const orc_edge_key* b = (const orc_edge_key*)pb;
+    if (a->w < b->w) return -1;
+    if (b->w < a->w) return 1;
+    if (a->id < b->id) return -1;
+    if (a->id > b->id) return 1;
+    return 0;
+}
+
+/* Union-find with path halving.  parent[x] == x marks a root. */
+static int32_t orc_find(int32_t* parent, int32_t x)
+{
+    while (parent[x] != x) {
+        parent[x] = parent[parent[x]];
+        x = parent[x];
+    }
+    return x;
+}
+
+/*
+ * Sort edge ids 0..m-1 by (w, id) ascending into order[].  Returns a status.
+ * Exposed on its own so tests can check the ordering step by itself.
+ */
+int oracle_edge_order(int64_t m, const float* w, int32_t* order)
+{
+    if (m < 0 || (m > 0 && (!w || !order))) return ORC_INVALID_ARG;
+    orc_edge_key* keys = (orc_edge_key*)malloc((size_t)(m > 0 ? m : 1) * sizeof(orc_edge_key));
+    if (!keys) return ORC_INVALID_ARG;
+    for (int64_t i = 0; i < m; ++i) {
+        if (isnan(w[i])) { free(keys); return ORC_NAN_WEIGHT; }
+        keys[i].w = w[i];
+        keys[i].id = (int32_t)i;
+    }
+    qsort(keys, (size_t)m, sizeof(orc_edge_key), orc_cmp);
+    for (int64_t i = 0; i < m; ++i) order[i] = keys[i].id;
+    free(keys);
+    return ORC_OK;
+}
+
+/*
+ * Dendrogram of one tree with n vertices and n-1 edges; edge i joins u[i] and
+ * v[i] with weight w[i].  Writes edge_parent[n-1] and vertex_parent[n] (input
+ * edge ids, -1 for "no parent").  All pointers are host pointers owned by the
+ * caller.
+ */
+int oracle_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                      int32_t* edge_parent, int32_t* vertex_parent)
+{
+    if (n < 1 || n > INT32_MAX) return ORC_INVALID_ARG;
+    const int64_t m = n - 1;
+    if (!vertex_parent) return ORC_INVALID_ARG;
+    if (m > 0 && (!u || !v || !w || !edge_parent)) return ORC_INVALID_ARG;
+
+    for (int64_t i = 0; i < m; ++i)
+        if (u[i] < 0 || u[i] >= n || v[i] < 0 || v[i] >= n) return ORC_BAD_VERTEX;
+
+    int32_t* order = (int32_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int32_t* parent = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    int32_t* size = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    int32_t* top = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    if (!order || !parent || !size || !top) {
+        free(order); free(parent); free(size); free(top);
+        return ORC_INVALID_ARG;
+    }
+
+    int status = oracle_edge_order(m, w, order);
+    if (status != ORC_OK) goto done;
+
+    for (int64_t x = 0; x < n; ++x) {
+        parent[x] = (int32_t)x;
+        size[x] = 1;
+        top[x] = -1;          /* -1: the cluster is still the single vertex x */
+        vertex_parent[x] = -1;
+    }
+    for (int64_t i = 0; i < m; ++i) edge_parent[i] = -1;
+
+    for (int64_t k = 0; k < m; ++k) {
+        const int32_t e = order[k];
+        const int32_t a = orc_find(parent, u[e]);
+        const int32_t b = orc_find(parent, v[e]);
+        if (a == b) { status = ORC_NOT_A_TREE; goto done; }
+        /* e becomes the parent of the node standing for each merged cluster. */
+        const int32_t ends[2] = {a, b};
+        for (int s = 0; s < 2; ++s) {
+            const int32_t x = ends[s];
+            if (top[x] < 0) vertex_parent[x] = e;   /* singleton: x is the vertex */
+            else edge_parent[top[x]] = e;
+        }
+        /* union by size; the merged cluster is now represented by edge e */
+        int32_t r = a, c = b;
+        if (size[r] < size[c]) { r = b; c = a; }
+        parent[c] = r;
+        size[r] += size[c];
+        top[r] = e;
+    }
+    /* The heaviest edge is the root and keeps edge_parent == -1. */
+
+done:
+    free(order); free(parent); free(size); free(top);
+    return status;
+}
+
+/*
+ * Batched form: B independent trees.  Tree b owns global vertices
+ * [voff[b], voff[b+1]) and global edges [voff[b]-b, voff[b+1]-b-1).  u, v and
+ * both outputs use TREE-LOCAL indices.  Each tree is built by
+ * oracle_dendrogram on its own slice; the first failing tree's status is
+ * returned (its index in *bad_tree when bad_tree is not NULL).
+ */
+int oracle_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
+                              const float* w, int32_t* edge_parent, int32_t* vertex_parent,
+                              int32_t* bad_tree)
+{
+    if (B < 1 || !voff) return ORC_INVALID_ARG;
+    if (voff[0] != 0) return ORC_INVALID_ARG;
+    for (int32_t b = 0; b < B; ++b)
+        if (voff[b + 1] - voff[b] < 1) return ORC_INVALID_ARG;
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t v0 = voff[b], nb = voff[b + 1] - voff[b];
+        const int64_t e0 = v0 - b;
+        int st = oracle_dendrogram(nb, u ? u + e0 : NULL, v ? v + e0 : NULL, w ? w + e0 : NULL,
+                                   edge_parent ? edge_parent + e0 : NULL, vertex_parent + v0);
+        if (st != ORC_OK) {
+            if (bad_tree) *bad_tree = b;
+            return st;
+        }
+    }
+    return ORC_OK;
+}
