@@ -1,0 +1,106 @@
+/*
+ * pandora.h -- C ABI of libpandora.so: single-linkage dendrograms of minimum
+ * spanning trees on an MI355X (gfx950), by recursive tree contraction.
+ *
+ * Method: Algorithm 1 of the paper ("Dendrogram Computation using Tree
+ * Contraction", Section 3): sort the MST edges by weight (Section 3.1.1),
+ * contract all non-alpha edges level by level (Section 3.2, Eq. alphaedge),
+ * then expand: map every edge to a leaf chain of some level or to the root
+ * chain (Section 3.3.2), sort the chains and stitch them (Section 3.3.3).
+ *
+ * Problem statement (Algorithm 1's input; Section 3.1.2 defines the output):
+ * a tree with n vertices and n-1 edges, edge i joining u[i] and v[i] with
+ * fp32 weight w[i].  Edges are totally ordered by (w, i) ascending: equal
+ * weights fall to the lower edge id, and -0.0 ties with +0.0.  The
+ * dendrogram is the parent function P over vertices and edges:
+ *   edge_parent[i]   = id of the edge that merges edge i's cluster next
+ *                      (-1 for the heaviest edge, the root);
+ *   vertex_parent[x] = id of the lightest edge incident to x (Eq.
+ *                      vertexparent; -1 when x has no edge, i.e. n == 1).
+ * All ids are INPUT edge ids.
+ *
+ * Memory: every array pointer is a DEVICE pointer on the current HIP device,
+ * owned by the caller; the library never frees caller memory.  Scratch space
+ * is cached per (device, stream) and grows on demand (see
+ * pandora_workspace_bytes / pandora_release_workspaces).
+ *
+ * Execution: work is enqueued on `hip_stream` (NULL = the default stream).
+ * The call returns when the dendrogram is complete: contraction reads one
+ * small counter block back per large level, so the host waits for the
+ * stream.  Calls on different streams may run concurrently from different
+ * host threads; calls on the same stream are serialized.
+ *
+ * Errors: the return value is a pandora_status_t.  Argument errors are
+ * detected before any work is enqueued.  Input errors (ids out of range, NaN
+ * weights, cycles/disconnected input) are detected on the device; the
+ * outputs are then unspecified but every kernel still stays within its
+ * buffers.  When several input errors are present the first of
+ * BAD_VERTEX, NAN_WEIGHT, NOT_A_TREE is reported.
+ */
+#ifndef PANDORA_H
+#define PANDORA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PANDORA_OK = 0,
+    PANDORA_ERR_INVALID_ARG = 1,   /* bad size, null pointer, bad offsets */
+    PANDORA_ERR_NOT_A_TREE = 2,    /* cycle / disconnected graph / self loop */
+    PANDORA_ERR_NAN_WEIGHT = 3,    /* some w[i] is NaN */
+    PANDORA_ERR_OUT_OF_MEMORY = 4, /* scratch allocation failed */
+    PANDORA_ERR_HIP = 5,           /* HIP runtime error or internal check */
+    PANDORA_ERR_BAD_VERTEX = 6     /* some u[i]/v[i] outside [0, n) of its tree */
+} pandora_status_t;
+
+/*
+ * Dendrogram of one tree.
+ *   n              number of vertices, 1 <= n <= 2^31 - 1 (edges: n-1)
+ *   u, v           int32[n-1] edge endpoints in [0, n)      (device)
+ *   w              float[n-1] edge weights, no NaN          (device)
+ *   edge_parent    int32[n-1] output                        (device)
+ *   vertex_parent  int32[n]   output                        (device)
+ *   hip_stream     hipStream_t to enqueue on, or NULL
+ * For n == 1 the edge arrays may be NULL.
+ */
+int pandora_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                       int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream);
+
+/*
+ * Dendrograms of B independent trees in one pass (a forest).  Tree b owns
+ * vertices [voff[b], voff[b+1]) and edges [voff[b]-b, voff[b+1]-b-1) of the
+ * concatenated arrays; voff is a HOST int64[B+1] array with voff[0] = 0 and
+ * voff[b+1] > voff[b].  u, v and both outputs use TREE-LOCAL ids: u/v of tree
+ * b are in [0, voff[b+1]-voff[b]), and edge ids in the outputs count from
+ * the tree's first edge.  Each tree's result is identical to what
+ * pandora_dendrogram returns for it alone.
+ */
+int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
+                               const float* w, int32_t* edge_parent, int32_t* vertex_parent,
+                               void* hip_stream);
+
+/* Device scratch bytes a call with n_total_vertices over B trees needs
+ * (admission control and preallocation).  0 on invalid sizes. */
+size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B);
+
+/* Per-stage statistics of the last successful call on this thread:
+ * out[0] = levels, out[1] = sum of edges over all levels, out[2] = pointer
+ * jumping launches, out[3] = levels done in the LDS tail, out[4] = edges at
+ * the level the LDS tail started from.  Returns the number filled (<= cap). */
+int pandora_last_stats(int64_t* out, int cap);
+
+/* Free every cached scratch allocation (waits for the owning streams). */
+void pandora_release_workspaces(void);
+
+/* Human-readable name of a status code (static string). */
+const char* pandora_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PANDORA_H */

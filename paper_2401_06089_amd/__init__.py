@@ -1,0 +1,168 @@
+"""Single-linkage dendrograms of minimum spanning trees on MI355X (gfx950).
+
+Thin binding over ``libpandora.so`` (C ABI in ``include/pandora.h``): it only
+checks and marshals torch tensors; every step of the method runs in the
+library's HIP kernels.  PyTorch supplies device memory and the stream.
+
+    ep, vp = dendrogram(u, v, w)             # one tree, device tensors
+    ep, vp = dendrogram_batched(voff, u, v, w)  # a forest, tree-local ids
+
+The library is not optional: importing this package raises if it has not
+been built (``python -m paper_2401_06089_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpandora.so")
+
+OK = 0
+INVALID_ARG = 1
+NOT_A_TREE = 2
+NAN_WEIGHT = 3
+OUT_OF_MEMORY = 4
+HIP_ERROR = 5
+BAD_VERTEX = 6
+
+
+class PandoraError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pandora status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_06089_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.pandora_dendrogram.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.pandora_dendrogram.restype = ctypes.c_int
+    lib.pandora_dendrogram_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+    lib.pandora_dendrogram_batched.restype = ctypes.c_int
+    lib.pandora_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    lib.pandora_workspace_bytes.restype = ctypes.c_size_t
+    lib.pandora_last_stats.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.pandora_last_stats.restype = ctypes.c_int
+    lib.pandora_release_workspaces.argtypes = []
+    lib.pandora_release_workspaces.restype = None
+    lib.pandora_status_string.argtypes = [ctypes.c_int]
+    lib.pandora_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def library() -> ctypes.CDLL:
+    """The loaded ctypes handle of libpandora.so."""
+    return _load()
+
+
+def status_string(status: int) -> str:
+    return _load().pandora_status_string(int(status)).decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise PandoraError(status, status_string(status))
+
+
+def _dptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _as_dev(t, dtype, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError("inputs must be device tensors")
+    if t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def dendrogram_into(n: int, u, v, w, edge_parent, vertex_parent, stream=None) -> int:
+    """Raw call: writes into preallocated int32 device tensors; returns the status."""
+    return _load().pandora_dendrogram(int(n), _dptr(u), _dptr(v), _dptr(w), _dptr(edge_parent),
+                                      _dptr(vertex_parent), _stream_handle(stream))
+
+
+def dendrogram(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
+               n: Optional[int] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Dendrogram of one tree with n = len(w) + 1 vertices.
+
+    u, v: int32 device tensors of edge endpoints; w: float32 weights.
+    Returns (edge_parent[n-1], vertex_parent[n]) as int32 device tensors.
+    """
+    m = w.numel()
+    if n is None:
+        n = m + 1
+    if n != m + 1 or u.numel() != m or v.numel() != m:
+        raise ValueError("a tree with n vertices has n-1 edges")
+    dev = w.device
+    u = _as_dev(u, torch.int32, dev)
+    v = _as_dev(v, torch.int32, dev)
+    w = _as_dev(w, torch.float32, dev)
+    with torch.cuda.device(dev):
+        ep = torch.empty(m, dtype=torch.int32, device=dev)
+        vp = torch.empty(n, dtype=torch.int32, device=dev)
+        _check(dendrogram_into(n, u, v, w, ep, vp, stream))
+    return ep, vp
+
+
+def dendrogram_batched(voff, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
+                       stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Dendrograms of B trees at once.  voff: host int64 offsets (B+1, numpy or
+    CPU tensor); tree b owns vertices [voff[b], voff[b+1]) and edges
+    [voff[b]-b, voff[b+1]-b-1).  u, v and the outputs use tree-local ids."""
+    voff_t = torch.as_tensor(voff, dtype=torch.int64).cpu().contiguous()
+    B = voff_t.numel() - 1
+    if B < 1:
+        raise ValueError("need at least one tree")
+    N = int(voff_t[-1])
+    M = N - B
+    if w.numel() != M or u.numel() != M or v.numel() != M:
+        raise ValueError("edge arrays must hold voff[-1] - B entries")
+    dev = w.device
+    u = _as_dev(u, torch.int32, dev)
+    v = _as_dev(v, torch.int32, dev)
+    w = _as_dev(w, torch.float32, dev)
+    with torch.cuda.device(dev):
+        ep = torch.empty(M, dtype=torch.int32, device=dev)
+        vp = torch.empty(N, dtype=torch.int32, device=dev)
+        st = _load().pandora_dendrogram_batched(
+            B, ctypes.c_void_p(voff_t.data_ptr()), _dptr(u), _dptr(v), _dptr(w), _dptr(ep), _dptr(vp),
+            _stream_handle(stream))
+        _check(st)
+    return ep, vp
+
+
+def workspace_bytes(n_total_vertices: int, trees: int = 1) -> int:
+    return int(_load().pandora_workspace_bytes(int(n_total_vertices), int(trees)))
+
+
+def last_stats() -> dict:
+    buf = (ctypes.c_int64 * 5)()
+    k = _load().pandora_last_stats(buf, 5)
+    names = ["levels", "sum_level_edges", "jump_launches", "tail_levels", "tail_entry_edges"]
+    return {names[i]: int(buf[i]) for i in range(k)}
+
+
+def release_workspaces():
+    _load().pandora_release_workspaces()

@@ -1,0 +1,101 @@
+// Shared device helpers for the dendrogram kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pandora {
+
+constexpr int kWave = 64;
+constexpr int32_t kInf = 0x7fffffff;   // "no incident edge" rank
+
+// Deferred error bits, OR-ed into Control::err by the kernels.
+enum : uint32_t {
+    kErrNaN = 1u << 0,        // a weight is NaN
+    kErrBadVertex = 1u << 1,  // a vertex id outside its tree
+    kErrNotTree = 1u << 2,    // cycle / disconnected input
+    kErrOverflow = 1u << 3,   // a level outgrew the tree bound (=> not a tree)
+    kErrSpin = 1u << 4,       // a look-back wait hit its spin limit
+    kErrWalk = 1u << 5,       // the expansion walk left the level tables
+};
+
+// Device-resident control block; zeroed at the start of every call.
+struct Control {
+    uint32_t err;
+    uint32_t not_converged;   // pointer jumping left a vertex short of its root
+    uint32_t isolated;        // isolated vertices seen (= finished components)
+    uint32_t alpha_tiles;     // dynamic tile counter of the alpha/leaf scan
+    int32_t m_next;           // alpha edges at the current level  (= m_{j+1})
+    int32_t n_next;           // leaf edges at the current level   (= n_{j+1})
+    int32_t tail_levels;      // levels finished inside the LDS tail kernel
+    int32_t tail_vertices;    // vertices of the last level (all isolated)
+    uint32_t sort_tiles[8];   // dynamic tile counters, one per radix pass
+    uint32_t hist[8][256];    // per-pass digit histograms (8-bit digits)
+};
+
+// A forest of B trees: tree b owns vertices [voff[b], voff[b+1]) and edges
+// [voff[b]-b, voff[b+1]-b-1).  A single tree is B = 1, voff = {0, n}.
+struct Forest {
+    const int64_t* voff;   // device copy, B+1 entries
+    int32_t B;
+
+    __device__ __forceinline__ int32_t tree_of_edge(int64_t e) const {
+        if (B == 1) return 0;
+        int32_t lo = 0, hi = B - 1;          // largest b with voff[b]-b <= e
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (voff[mid] - mid <= e) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    __device__ __forceinline__ int32_t tree_of_vertex(int64_t x) const {
+        if (B == 1) return 0;
+        int32_t lo = 0, hi = B - 1;          // largest b with voff[b] <= x
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (voff[mid] <= x) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    __device__ __forceinline__ int64_t edge_base(int32_t b) const { return voff[b] - b; }
+};
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+// Agent-scope relaxed atomics for cross-workgroup look-back words.  The word
+// itself carries all the information, so no fences are needed.
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void raise_err(Control* c, uint32_t bits) { atomicOr(&c->err, bits); }
+
+// Inclusive wave64 prefix sum.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, kWave);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+// Monotone u32 key of an fp32 weight: -0.0 is folded onto +0.0 so that the
+// two tie (and fall to the edge id); negatives flip all bits, non-negatives
+// flip the sign bit.  NaN is reported by the caller.
+__device__ __forceinline__ uint32_t weight_key(float w) {
+    uint32_t b = __float_as_uint(w);
+    if (b == 0x80000000u) b = 0u;
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ bool is_nan_bits(float w) {
+    return (__float_as_uint(w) & 0x7fffffffu) > 0x7f800000u;
+}
+
+}  // namespace pandora

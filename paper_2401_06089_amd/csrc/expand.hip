@@ -1,0 +1,117 @@
+// Dendrogram expansion (paper, Sections 3.3.2 and 3.3.3) on gfx950.
+//
+// Chain assignment.  An edge e of rank r that was contracted at level l into
+// the supervertex S of level l+1 is tested against S's lightest incident
+// edge p = minInc_{l+1}(S): if r < p, e belongs to the leaf chain of S at that
+// level, whose head hangs below p.  Otherwise S is itself contracted at level
+// l+1 and the test repeats one level up with S's own supervertex.  A vertex
+// with no incident edge (the last level, or a finished component of a forest)
+// has p = +inf and ends the walk: that is the component's root chain.  With
+// the flat vertex numbering the walk is a pointer chase
+//   x <- svflat[r];  while (r >= minInc_all[x]) x <- label_all[x];
+// and the final x identifies the chain (k_walk_hist, which also histograms
+// the chain keys for the sort that follows).
+//
+// Chain construction.  A stable sort of ranks by chain key lists every chain
+// lightest first.  Each edge's parent is the next, heavier edge of its chain;
+// the heaviest edge of a chain hangs below the chain's head edge p, or is the
+// dendrogram root when p = +inf (k_stitch).  Outputs use input edge ids.
+#include "kernels.hpp"
+
+namespace pandora {
+
+namespace {
+
+constexpr int kWalkLimit = 64;
+
+__global__ __launch_bounds__(256) void k_walk_hist(WalkArgs a) {
+    __shared__ uint32_t s_h[4][kRadix];
+    for (int i = threadIdx.x; i < 4 * kRadix; i += blockDim.x) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    for (int64_t r = t0; r < a.m; r += stride) {
+        int64_t x = a.svflat[r];
+        for (int it = 0;; ++it) {
+            if (x < a.n0 || x >= a.flat_cap || it >= kWalkLimit) {
+                bad = true;
+                x = a.n0;
+                break;
+            }
+            if (r < (int64_t)a.minInc_all[x]) break;
+            x = a.label_all[x];
+        }
+        const uint32_t key = (uint32_t)(x - a.n0);
+        a.ckey[r] = key;
+        for (int p = 0; p < a.passes; ++p)
+            atomicAdd(&s_h[p][(key >> (kSortBits * p)) & (kRadix - 1)], 1u);
+    }
+    for (int64_t i = t0; i < a.lb_zero_words; i += stride) a.lb_zero[i] = 0;
+    if (ballot(bad) != 0 && lane_id() == 0) raise_err(a.ctrl, kErrWalk);
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.passes * kRadix; i += blockDim.x) {
+        const uint32_t c = (&s_h[0][0])[i];
+        if (c) atomicAdd(&a.ctrl->hist[a.hist_row + i / kRadix][i % kRadix], c);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.m) return;
+    const uint32_t c = a.skey[i];
+    const int32_t id = a.sid[i];
+    if (id < 0 || id >= a.m || (int64_t)c >= a.flat_cap - a.n0) return;   // only after a reported error
+    int32_t parent;
+    if (i + 1 < a.m && a.skey[i + 1] == c) {
+        parent = a.sid[i + 1];
+    } else {
+        const int32_t p = a.minInc_all[a.n0 + (int64_t)c];
+        parent = (p < 0 || p >= a.m) ? -1 : a.perm[p];
+    }
+    if (parent >= 0 && a.forest.B > 1)
+        parent = (int32_t)(parent - a.forest.edge_base(a.forest.tree_of_edge(id)));
+    a.edge_parent[id] = parent;
+}
+
+__global__ void k_zero_control(Control* c) {
+    uint32_t* p = reinterpret_cast<uint32_t*>(c);
+    const int words = (int)(sizeof(Control) / sizeof(uint32_t));
+    for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t value) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = value;
+}
+
+}  // namespace
+
+hipError_t launch_walk_hist(const WalkArgs& a, hipStream_t s) {
+    int64_t blocks = (a.m + 256 * 8 - 1) / (256 * 8);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 8192) blocks = 8192;
+    k_walk_hist<<<(unsigned)blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stitch(const StitchArgs& a, hipStream_t s) {
+    if (a.m < 1) return hipSuccess;
+    k_stitch<<<(unsigned)((a.m + 255) / 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_control(Control* c, hipStream_t s) {
+    k_zero_control<<<1, 256, 0, s>>>(c);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s) {
+    if (n < 1) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_fill_i32<<<(unsigned)blocks, 256, 0, s>>>(p, n, value);
+    return hipGetLastError();
+}
+
+}  // namespace pandora

@@ -1,0 +1,158 @@
+// Kernel argument blocks and host-side launchers (internal interface between
+// the orchestration code and the .hip kernel files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace pandora {
+
+// ---- radix sort (stable LSD, 8-bit digits, one-sweep chained scan) ----------
+constexpr int kSortBits = 8;
+constexpr int kRadix = 1 << kSortBits;
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;   // 4096 keys per workgroup
+
+enum SortSrc { SRC_WEIGHT = 0, SRC_KEYS = 1 };
+enum SortDst { DST_KEYS = 0, DST_EDGES = 1 };
+
+struct SortPassArgs {
+    int64_t n;
+    int shift;                 // bit offset of this pass's digit
+    int pass;                  // row of Control::hist / sort_tiles
+    const float* w;            // SRC_WEIGHT: keys from weights, values = index
+    const uint32_t* keys_in;   // SRC_KEYS
+    const int32_t* vals_in;    // SRC_KEYS
+    uint32_t* keys_out;        // DST_KEYS
+    int32_t* vals_out;         // DST_KEYS values; DST_EDGES: perm (rank -> edge id)
+    const int32_t* u;          // DST_EDGES: input endpoints (tree-local ids)
+    const int32_t* v;
+    int32_t* ur;               // DST_EDGES: endpoints in rank order (global ids)
+    int32_t* vr;
+    Forest forest;
+    uint64_t* lb;              // look-back words of this pass, [tiles][kRadix]
+    uint64_t* lb_zero;         // look-back words of the next pass, cleared here
+    int64_t lb_zero_words;
+    Control* ctrl;
+};
+
+struct SortHistArgs {
+    int64_t n;
+    int hist_row;              // first Control::hist row written
+    int passes;                // digits histogrammed (<= 4)
+    const float* w;            // SRC_WEIGHT
+    const uint32_t* keys;      // SRC_KEYS
+    int32_t* fill;             // optional: fill[0..fill_n) = kInf
+    int64_t fill_n;
+    uint64_t* lb_zero;         // look-back words of the first pass, cleared here
+    int64_t lb_zero_words;
+    Control* ctrl;
+};
+
+hipError_t launch_sort_hist(int src, const SortHistArgs& a, hipStream_t s);
+hipError_t launch_sort_pass(int src, int dst, const SortPassArgs& a, hipStream_t s);
+
+__host__ __device__ inline int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+// ---- contraction levels -------------------------------------------------------
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;   // 2048 edges per workgroup
+
+__host__ __device__ inline int64_t scan_tiles(int64_t m) { return (m + kScanTile - 1) / kScanTile; }
+
+struct LevelArgs {
+    int32_t m;                 // edges at this level
+    int32_t n;                 // vertices at this level
+    const int32_t* eu;         // endpoints (level-local vertex ids)
+    const int32_t* ev;
+    const int32_t* er;         // global rank of each edge (nullptr at level 0)
+    int32_t* minInc;           // lightest incident rank per vertex (flat table + off_j)
+    int32_t* label;            // flat id of the supervertex at j+1 (flat table + off_j)
+    int32_t* minInc_next;      // flat table + off_{j+1}
+    int64_t off_next;          // flat offset of level j+1
+    int32_t* ptr;              // contraction pointers (level-local ids)
+    uint8_t* alpha;            // per-edge alpha flag
+    uint64_t* scan_lb;         // look-back words, one per scan tile
+    int32_t* tile_alpha_excl;  // alpha prefix at the start of each scan tile
+    int32_t* out_u;            // next level edges
+    int32_t* out_v;
+    int32_t* out_r;
+    int32_t cap_next_e;
+    int32_t cap_next_v;
+    int32_t* svflat;           // per rank: flat id of the supervertex an edge is contracted into
+    const int32_t* perm;       // level 0: rank -> global edge id
+    int32_t* vertex_parent;    // level 0 output (tree-local edge ids)
+    Forest forest;
+    Control* ctrl;
+    int jump_steps;
+    int round;
+};
+
+hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s);
+hipError_t launch_alpha_hook(bool level0, const LevelArgs& a, hipStream_t s);
+hipError_t launch_jump(bool level0, const LevelArgs& a, hipStream_t s);
+hipError_t launch_compact(bool level0, const LevelArgs& a, hipStream_t s);
+
+// All remaining levels inside one workgroup's LDS.
+constexpr int kTailThreads = 1024;
+constexpr int kTailE = 4096;
+constexpr int kTailV = 8192;
+
+struct TailArgs {
+    int32_t m;
+    int32_t n;
+    const int32_t* eu;
+    const int32_t* ev;
+    const int32_t* er;         // nullptr at level 0
+    int64_t off;               // flat offset of the entry level
+    int64_t flat_cap;
+    int32_t* minInc_all;
+    int32_t* label_all;
+    int32_t* svflat;
+    const int32_t* perm;
+    int32_t* vertex_parent;
+    Forest forest;
+    Control* ctrl;
+};
+
+hipError_t launch_tail(const TailArgs& a, hipStream_t s);
+
+// ---- expansion ----------------------------------------------------------------
+struct WalkArgs {
+    int64_t m;
+    int64_t n0;                // vertices of level 0 = flat offset of level 1
+    int64_t flat_cap;
+    const int32_t* svflat;
+    const int32_t* minInc_all;
+    const int32_t* label_all;
+    uint32_t* ckey;            // out: chain key per rank
+    int hist_row;
+    int passes;
+    uint64_t* lb_zero;
+    int64_t lb_zero_words;
+    Control* ctrl;
+};
+
+struct StitchArgs {
+    int64_t m;
+    int64_t n0;
+    int64_t flat_cap;
+    const uint32_t* skey;      // chain keys sorted
+    const int32_t* sid;        // edge ids in chain order
+    const int32_t* minInc_all;
+    const int32_t* perm;
+    int32_t* edge_parent;
+    Forest forest;
+};
+
+hipError_t launch_walk_hist(const WalkArgs& a, hipStream_t s);
+hipError_t launch_stitch(const StitchArgs& a, hipStream_t s);
+
+// ---- misc -----------------------------------------------------------------------
+hipError_t launch_zero_control(Control* c, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s);
+
+}  // namespace pandora

@@ -1,0 +1,497 @@
+// Recursive tree contraction (paper, Section 3.2) on gfx950.
+//
+// Level j holds m_j edges in ascending rank order (rank = position in the
+// global (weight, id) order; the paper indexes the same order descending) and
+// n_j vertices.  One level does:
+//
+//   k_min_incident  minInc[x] = lightest incident rank of x.  This is the
+//                   paper's maxIncident (Eq. vertexparent) in ascending ranks;
+//                   at level 0 it is also every vertex's dendrogram parent.
+//   k_alpha_hook    alpha test of Eq. (alphaedge): an edge is alpha iff it is
+//                   the lightest edge of neither endpoint.  Every other edge is
+//                   contracted.  A vertex x points along its lightest edge
+//                   (ptr[x] = other endpoint); ranks strictly fall along
+//                   pointers except across a leaf edge (lightest at both ends),
+//                   whose smaller endpoint becomes the root.  Each supervertex
+//                   therefore is one pointer tree rooted at its unique leaf edge,
+//                   and the supervertices of T_{j+1} are numbered by an
+//                   exclusive scan of leaf flags in rank order (decoupled
+//                   look-back across tiles, alpha count scanned alongside).
+//   k_jump          pointer jumping (in place, bounded steps per launch; the
+//                   host relaunches until every vertex reaches its root), then
+//                   each vertex takes its root's flat label.
+//   k_compact       stable compaction of alpha edges into level j+1 (endpoints
+//                   relabelled, rank kept, so level j+1 is again rank-sorted);
+//                   every contracted edge records the flat id of the
+//                   supervertex it fell into (needed by the expansion).
+//
+// Vertices and levels share one flat id space: level j occupies
+// [off_j, off_j + n_j).  Isolated vertices (finished components of a forest)
+// are not carried to the next level.
+//
+// k_tail runs every remaining level inside one workgroup's LDS once a level
+// is small, replacing ~4 launches and one host round trip per level.
+#include "kernels.hpp"
+
+namespace pandora {
+
+namespace {
+
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagInc = 2ull << 62;
+constexpr uint64_t kFlagMask = 3ull << 62;
+constexpr uint64_t kCountMask = ~kFlagMask;
+constexpr uint64_t kLow31 = (1ull << 31) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ int32_t local_edge_id(const Forest& f, int32_t gid) {
+    if (f.B == 1) return gid;
+    return (int32_t)(gid - f.edge_base(f.tree_of_edge(gid)));
+}
+
+template <bool L0>
+__global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < scan_tiles(a.m)) a.scan_lb[i] = 0;
+    if (i == 0) {
+        a.ctrl->alpha_tiles = 0;
+        a.ctrl->not_converged = 0;
+    }
+    if (i >= a.m) return;
+    const int32_t r = L0 ? (int32_t)i : a.er[i];
+    const int32_t x = a.eu[i];
+    const int32_t y = a.ev[i];
+    // Test first: values only decrease, so a stale read can only cause a
+    // redundant atomic, never a missed one.
+    if (a.minInc[x] > r) atomicMin(&a.minInc[x], r);
+    if (a.minInc[y] > r) atomicMin(&a.minInc[y], r);
+}
+
+template <bool L0>
+__global__ __launch_bounds__(kScanBlock) void k_alpha_hook(LevelArgs a) {
+    constexpr int W = kScanBlock / kWave;
+    __shared__ uint32_t s_ca[kScanItems][W];
+    __shared__ uint32_t s_cl[kScanItems][W];
+    __shared__ uint64_t s_excl;
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    if (tid == 0) s_tile = atomicAdd(&a.ctrl->alpha_tiles, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * kScanTile;
+    const uint64_t lt = lanemask_lt();
+
+    uint32_t lmask = 0;
+    uint32_t lpre[kScanItems];
+    int32_t root[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t idx = base + k * kScanBlock + tid;
+        bool al = false, lf = false;
+        root[k] = 0;
+        if (idx < a.m) {
+            const int32_t r = L0 ? (int32_t)idx : a.er[idx];
+            const int32_t x = a.eu[idx];
+            const int32_t y = a.ev[idx];
+            const bool ax = a.minInc[x] == r;
+            const bool ay = a.minInc[y] == r;
+            if (ax && ay) {
+                const int32_t lo = x < y ? x : y;
+                const int32_t hi = x < y ? y : x;
+                a.ptr[lo] = lo;
+                a.ptr[hi] = lo;
+                lf = true;
+                root[k] = lo;
+            } else if (ax) {
+                a.ptr[x] = y;
+            } else if (ay) {
+                a.ptr[y] = x;
+            } else {
+                al = true;
+            }
+            a.alpha[idx] = al ? 1 : 0;
+        }
+        const uint64_t ba = ballot(al);
+        const uint64_t bl = ballot(lf);
+        lpre[k] = (uint32_t)popc64(bl & lt);
+        lmask |= (lf ? 1u : 0u) << k;
+        if (lane == 0) {
+            s_ca[k][wave] = (uint32_t)popc64(ba);
+            s_cl[k][wave] = (uint32_t)popc64(bl);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t sa = 0, sl = 0;
+        for (int k = 0; k < kScanItems; ++k)
+            for (int w = 0; w < W; ++w) {
+                const uint32_t ca = s_ca[k][w], cl = s_cl[k][w];
+                s_ca[k][w] = sa;
+                s_cl[k][w] = sl;
+                sa += ca;
+                sl += cl;
+            }
+        const uint64_t agg = ((uint64_t)sa << 31) | (uint64_t)sl;
+        uint64_t* my = a.scan_lb + tile;
+        st_relaxed(my, (tile == 0 ? kFlagInc : kFlagAgg) | agg);
+        uint64_t excl = 0;
+        if (tile > 0) {
+            int64_t p = tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const uint64_t wv = ld_relaxed(a.scan_lb + p);
+                const uint64_t flag = wv & kFlagMask;
+                if (flag == 0) {
+                    if (++spins > kSpinLimit) {
+                        raise_err(a.ctrl, kErrSpin);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                spins = 0;
+                excl += wv & kCountMask;   // fields never carry: each sum < 2^31
+                if (flag == kFlagInc || p == 0) break;
+                --p;
+            }
+            st_relaxed(my, kFlagInc | (excl + agg));
+        }
+        s_excl = excl;
+        a.tile_alpha_excl[tile] = (int32_t)(excl >> 31);
+        if (tile == scan_tiles(a.m) - 1) {
+            const uint64_t all = excl + agg;
+            a.ctrl->m_next = (int32_t)(all >> 31);
+            a.ctrl->n_next = (int32_t)(all & kLow31);
+        }
+    }
+    __syncthreads();
+    const int64_t leaf_base = (int64_t)(s_excl & kLow31);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (lmask & (1u << k)) {
+            const int64_t pos = leaf_base + s_cl[k][wave] + lpre[k];
+            a.label[root[k]] = (int32_t)(a.off_next + pos);
+        }
+    }
+}
+
+template <bool L0>
+__global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
+    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= a.n) return;
+    const int32_t mi = a.minInc[x];
+    const bool isolated = mi == kInf;
+    if (a.round == 0) {
+        if (L0) {
+            int32_t vp = -1;
+            if (!isolated) {
+                vp = a.perm[mi];
+                if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex(x)));
+            }
+            a.vertex_parent[x] = vp;
+        }
+        int32_t nn = a.ctrl->n_next;
+        if (nn > a.cap_next_v) nn = a.cap_next_v;
+        if (x < nn) a.minInc_next[x] = kInf;
+        const uint64_t b = ballot(isolated);
+        if (b != 0 && (threadIdx.x & (kWave - 1)) == (uint32_t)__ffsll((long long)b) - 1)
+            atomicAdd(&a.ctrl->isolated, (uint32_t)popc64(b));
+        if (isolated) a.label[x] = -1;
+    }
+    if (isolated) return;
+    int32_t p = a.ptr[x];
+    if (p == x) return;                       // root: labelled by k_alpha_hook
+    int32_t pp = a.ptr[p];
+    for (int s = 0; pp != p && s < a.jump_steps; ++s) {
+        p = pp;
+        pp = a.ptr[p];
+    }
+    a.ptr[x] = p;
+    if (pp != p) {
+        atomicOr(&a.ctrl->not_converged, 1u << (a.round & 31));
+        return;
+    }
+    a.label[x] = a.label[p];
+}
+
+template <bool L0>
+__global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
+    constexpr int W = kScanBlock / kWave;
+    __shared__ uint32_t s_ca[kScanItems][W];
+    const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * kScanTile;
+    const uint64_t lt = lanemask_lt();
+    uint32_t amask = 0;
+    uint32_t apre[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t idx = base + k * kScanBlock + tid;
+        const bool al = idx < a.m && a.alpha[idx] != 0;
+        const uint64_t ba = ballot(al);
+        apre[k] = (uint32_t)popc64(ba & lt);
+        amask |= (al ? 1u : 0u) << k;
+        if (lane == 0) s_ca[k][wave] = (uint32_t)popc64(ba);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t sa = 0;
+        for (int k = 0; k < kScanItems; ++k)
+            for (int w = 0; w < W; ++w) {
+                const uint32_t c = s_ca[k][w];
+                s_ca[k][w] = sa;
+                sa += c;
+            }
+    }
+    __syncthreads();
+    const int64_t abase = a.tile_alpha_excl[tile];
+    bool selfloop = false, overflow = false;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t idx = base + k * kScanBlock + tid;
+        if (idx >= a.m) continue;
+        const int32_t r = L0 ? (int32_t)idx : a.er[idx];
+        const int32_t lx = a.label[a.eu[idx]];
+        if (amask & (1u << k)) {
+            const int32_t ly = a.label[a.ev[idx]];
+            const int64_t pos = abase + s_ca[k][wave] + apre[k];
+            selfloop |= lx == ly;
+            if (pos < a.cap_next_e) {
+                a.out_u[pos] = (int32_t)(lx - a.off_next);
+                a.out_v[pos] = (int32_t)(ly - a.off_next);
+                a.out_r[pos] = r;
+            } else {
+                overflow = true;
+            }
+        } else {
+            a.svflat[r] = lx;
+        }
+    }
+    if (ballot(selfloop) != 0 && lane == 0) raise_err(a.ctrl, kErrNotTree);
+    if (ballot(overflow) != 0 && lane == 0) raise_err(a.ctrl, kErrOverflow);
+}
+
+// ---- the LDS tail: all remaining levels in one workgroup ----------------------
+
+template <int BLOCK>
+__device__ __forceinline__ uint32_t tail_excl_scan(uint32_t x, uint32_t* s_wsum, uint32_t* total) {
+    constexpr int W = BLOCK / kWave;
+    const int wave = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane_id() == kWave - 1) s_wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t s = s_wsum[w];
+        if (w < wave) before += s;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
+}
+
+constexpr int kTailPer = kTailE / kTailThreads;   // edges per thread (blocked)
+
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
+    __shared__ int32_t s_u[kTailE], s_v[kTailE], s_r[kTailE];
+    __shared__ int32_t s_min[kTailV], s_ptr[kTailV], s_lab[kTailV];
+    __shared__ uint32_t s_wsum[kTailThreads / kWave];
+    __shared__ uint32_t s_flag;
+    const int tid = threadIdx.x;
+    const bool level0 = a.er == nullptr;
+
+    int32_t m = a.m, n = a.n;
+    int64_t off = a.off;
+    bool first = true;
+    int levels = 0;
+    uint32_t err = 0;
+    for (int i = tid; i < m; i += kTailThreads) {
+        s_u[i] = a.eu[i];
+        s_v[i] = a.ev[i];
+        s_r[i] = level0 ? i : a.er[i];
+    }
+    __syncthreads();
+
+    while (m > 0) {
+        const int64_t off_next = off + n;
+        // lightest incident rank
+        for (int x = tid; x < n; x += kTailThreads) s_min[x] = kInf;
+        __syncthreads();
+        for (int i = tid; i < m; i += kTailThreads) {
+            atomicMin(&s_min[s_u[i]], s_r[i]);
+            atomicMin(&s_min[s_v[i]], s_r[i]);
+        }
+        __syncthreads();
+        // alpha test, hooks, leaf/alpha counts (thread t owns edges [4t, 4t+4))
+        uint32_t amask = 0, lmask = 0, ca = 0, cl = 0;
+#pragma unroll
+        for (int q = 0; q < kTailPer; ++q) {
+            const int i = tid * kTailPer + q;
+            if (i >= m) break;
+            const int32_t r = s_r[i], x = s_u[i], y = s_v[i];
+            const bool ax = s_min[x] == r, ay = s_min[y] == r;
+            if (ax && ay) {
+                const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+                s_ptr[lo] = lo;
+                s_ptr[hi] = lo;
+                lmask |= 1u << q;
+                ++cl;
+            } else if (ax) {
+                s_ptr[x] = y;
+            } else if (ay) {
+                s_ptr[y] = x;
+            } else {
+                amask |= 1u << q;
+                ++ca;
+            }
+        }
+        uint32_t tot;
+        const uint32_t ex = tail_excl_scan<kTailThreads>(ca | (cl << 16), s_wsum, &tot);
+        const uint32_t A = tot & 0xffffu, L = tot >> 16;
+        uint32_t ea = ex & 0xffffu, el = ex >> 16;
+        for (int q = 0; q < kTailPer; ++q) {
+            if (lmask & (1u << q)) {
+                const int i = tid * kTailPer + q;
+                const int32_t lo = s_u[i] < s_v[i] ? s_u[i] : s_v[i];
+                s_lab[lo] = (int32_t)(off_next + el);
+                ++el;
+            }
+        }
+        __syncthreads();
+        // pointer jumping to the leaf-edge roots
+        int it = 0;
+        for (;; ++it) {
+            __syncthreads();
+            if (tid == 0) s_flag = 0;
+            __syncthreads();
+            bool changed = false;
+            for (int x = tid; x < n; x += kTailThreads) {
+                if (s_min[x] == kInf) continue;
+                const int32_t p = s_ptr[x], pp = s_ptr[p];
+                if (p != pp) {
+                    s_ptr[x] = pp;
+                    changed = true;
+                }
+            }
+            if (changed) s_flag = 1;
+            __syncthreads();
+            if (s_flag == 0 || it >= 64) break;
+        }
+        if (it >= 64) err |= kErrNotTree;
+        // labels and the level tables
+        uint32_t iso = 0;
+        for (int x = tid; x < n; x += kTailThreads) {
+            const int32_t mi = s_min[x];
+            int32_t lab = -1;
+            if (mi == kInf) ++iso;
+            else lab = s_lab[s_ptr[x]];
+            a.minInc_all[off + x] = mi;
+            a.label_all[off + x] = lab;
+            if (first && level0) {
+                int32_t vp = -1;
+                if (mi != kInf) {
+                    vp = a.perm[mi];
+                    if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex(x)));
+                }
+                a.vertex_parent[x] = vp;
+            }
+        }
+        if (iso) atomicAdd(&a.ctrl->isolated, iso);
+        __syncthreads();
+        for (int x = tid; x < n; x += kTailThreads)
+            if (s_min[x] != kInf) s_lab[x] = s_lab[s_ptr[x]];
+        __syncthreads();
+        // compaction: read everything first, then write (positions only move down)
+        int32_t nu[kTailPer], nv[kTailPer], nr[kTailPer];
+        for (int q = 0; q < kTailPer; ++q) {
+            const int i = tid * kTailPer + q;
+            if (i >= m) break;
+            const int32_t lx = s_lab[s_u[i]];
+            if (amask & (1u << q)) {
+                const int32_t ly = s_lab[s_v[i]];
+                if (lx == ly) err |= kErrNotTree;
+                nu[q] = (int32_t)(lx - off_next);
+                nv[q] = (int32_t)(ly - off_next);
+                nr[q] = s_r[i];
+            } else {
+                a.svflat[s_r[i]] = lx;
+            }
+        }
+        __syncthreads();
+        for (int q = 0; q < kTailPer; ++q) {
+            if (amask & (1u << q)) {
+                s_u[ea] = nu[q];
+                s_v[ea] = nv[q];
+                s_r[ea] = nr[q];
+                ++ea;
+            }
+        }
+        __syncthreads();
+        off = off_next;
+        n = (int32_t)L;
+        m = (int32_t)A;
+        first = false;
+        ++levels;
+        if (off + n > a.flat_cap) {
+            err |= kErrOverflow;
+            break;
+        }
+    }
+    // last level: no edges left, every vertex is its component's root chain
+    if (!err && off + n <= a.flat_cap) {
+        for (int x = tid; x < n; x += kTailThreads) {
+            a.minInc_all[off + x] = kInf;
+            a.label_all[off + x] = -1;
+            if (first && level0) a.vertex_parent[x] = -1;
+        }
+    }
+    if (err) raise_err(a.ctrl, err);
+    if (tid == 0) {
+        atomicAdd(&a.ctrl->isolated, (uint32_t)n);
+        a.ctrl->tail_levels = levels;
+        a.ctrl->tail_vertices = n;
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int per) {
+    const int64_t b = (n + per - 1) / per;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s) {
+    const int64_t work = a.m > scan_tiles(a.m) ? a.m : scan_tiles(a.m);
+    if (level0) k_min_incident<true><<<blocks_for(work, 256), 256, 0, s>>>(a);
+    else k_min_incident<false><<<blocks_for(work, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha_hook(bool level0, const LevelArgs& a, hipStream_t s) {
+    const unsigned g = (unsigned)scan_tiles(a.m);
+    if (level0) k_alpha_hook<true><<<g, kScanBlock, 0, s>>>(a);
+    else k_alpha_hook<false><<<g, kScanBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_jump(bool level0, const LevelArgs& a, hipStream_t s) {
+    if (level0) k_jump<true><<<blocks_for(a.n, 256), 256, 0, s>>>(a);
+    else k_jump<false><<<blocks_for(a.n, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(bool level0, const LevelArgs& a, hipStream_t s) {
+    const unsigned g = (unsigned)scan_tiles(a.m);
+    if (level0) k_compact<true><<<g, kScanBlock, 0, s>>>(a);
+    else k_compact<false><<<g, kScanBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail(const TailArgs& a, hipStream_t s) {
+    k_tail<<<1, kTailThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace pandora

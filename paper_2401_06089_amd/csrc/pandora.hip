@@ -1,0 +1,493 @@
+// Host orchestration and C ABI of libpandora.so (see include/pandora.h).
+//
+// One call runs Algorithm 1 of the paper on the device:
+//   1. weight sort: histogram + 4 one-sweep radix passes over the u32 image
+//      of the weights; the last pass emits perm (rank -> edge id) and the
+//      endpoints in rank order (global vertex ids for a forest);
+//   2. contraction levels while a level is large (k_min_incident,
+//      k_alpha_hook, k_jump until converged, k_compact), reading back one
+//      32-byte counter block per level to size the next one;
+//   3. every remaining level in one LDS-resident workgroup (k_tail);
+//   4. expansion: chain keys by the level walk (fused with the chain-key
+//      histogram), radix passes of (chain key, edge id), stitch.
+//
+// Scratch memory comes from one allocation per (device, stream), kept
+// between calls and grown on demand.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "kernels.hpp"
+#include "pandora.h"
+
+namespace pandora {
+namespace {
+
+constexpr int kJumpSteps = 16;
+constexpr int kMaxJumpRounds = 64;
+constexpr size_t kAlign = 256;
+constexpr size_t kCtrlReadback = 32;   // err .. tail_vertices
+
+struct Layout {
+    int64_t N = 0, M = 0;
+    int32_t B = 0;
+    int Lmax = 0;
+    std::vector<int64_t> capE, capV;
+    int64_t flat_cap = 0;
+    int chain_passes = 0;
+    size_t ctrl, voff, K0, K1, V0, V1, perm, ur, vr, EA[3], EB[3], alpha, scan_lb, tile_excl,
+        minInc, label, ptr, svflat, lb0, lb1;
+    size_t total = 0;
+};
+
+size_t take(size_t& cursor, size_t bytes) {
+    const size_t at = cursor;
+    cursor += (bytes + kAlign - 1) / kAlign * kAlign;
+    return at;
+}
+
+int ceil_log2(int64_t x) {   // smallest L with 2^L >= x (x >= 1)
+    int L = 0;
+    while ((int64_t(1) << L) < x) ++L;
+    return L;
+}
+
+Layout make_layout(int64_t N, int32_t B) {
+    Layout L;
+    L.N = N;
+    L.B = B;
+    L.M = N - B;
+    const int64_t M = L.M;
+    // Section 4.2: at most (m-1)/2 alpha edges per level, so at most
+    // ceil(log2(m+1)) levels; a level of a forest has at most m_j + B vertices.
+    L.Lmax = ceil_log2(M + 1) + 2;
+    L.capE.assign(L.Lmax + 2, 0);
+    L.capV.assign(L.Lmax + 2, 0);
+    L.capE[0] = M;
+    L.capV[0] = N;
+    for (int j = 1; j < (int)L.capE.size(); ++j) {
+        L.capE[j] = L.capE[j - 1] / 2;
+        L.capV[j] = std::min<int64_t>(L.capE[j] + B, N);
+    }
+    L.flat_cap = 0;
+    for (int64_t c : L.capV) L.flat_cap += c;
+    const int64_t key_range = std::max<int64_t>(L.flat_cap - N, 1);
+    int bits = 0;
+    while ((int64_t(1) << bits) < key_range) ++bits;
+    L.chain_passes = std::max(1, (bits + kSortBits - 1) / kSortBits);
+
+    const int64_t E1 = std::max<int64_t>(L.capE[1], 1), E2 = std::max<int64_t>(L.capE[2], 1);
+    const int64_t sortlb = sort_tiles(std::max<int64_t>(M, 1)) * kRadix;
+    const int64_t scant = scan_tiles(std::max<int64_t>(M, 1));
+    size_t c = 0;
+    L.ctrl = take(c, sizeof(Control));
+    L.voff = take(c, sizeof(int64_t) * (B + 1));
+    L.K0 = take(c, 4 * M);
+    L.K1 = take(c, 4 * M);
+    L.V0 = take(c, 4 * M);
+    L.V1 = take(c, 4 * M);
+    L.perm = take(c, 4 * M);
+    L.ur = take(c, 4 * M);
+    L.vr = take(c, 4 * M);
+    for (int k = 0; k < 3; ++k) L.EA[k] = take(c, 4 * E1);
+    for (int k = 0; k < 3; ++k) L.EB[k] = take(c, 4 * E2);
+    L.alpha = take(c, M);
+    L.scan_lb = take(c, 8 * scant);
+    L.tile_excl = take(c, 4 * scant);
+    L.minInc = take(c, 4 * L.flat_cap);
+    L.label = take(c, 4 * L.flat_cap);
+    L.ptr = take(c, 4 * N);
+    L.svflat = take(c, 4 * M);
+    L.lb0 = take(c, 8 * sortlb);
+    L.lb1 = take(c, 8 * sortlb);
+    L.total = c;
+    return L;
+}
+
+struct Workspace {
+    std::mutex mu;
+    void* dev = nullptr;
+    size_t bytes = 0;
+    void* host = nullptr;          // pinned: Control readback + voff staging
+    size_t host_bytes = 0;
+    hipStream_t stream = nullptr;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+
+struct Stats {
+    int64_t levels = 0, sum_edges = 0, jump_launches = 0, tail_levels = 0, tail_entry_edges = 0;
+};
+thread_local Stats g_last;
+
+Workspace* workspace_for(int dev, hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_mu);
+    auto& slot = g_ws[{dev, s}];
+    if (!slot) {
+        slot.reset(new Workspace);
+        slot->stream = s;
+    }
+    return slot.get();
+}
+
+int status_from_err(uint32_t err) {
+    if (err & kErrBadVertex) return PANDORA_ERR_BAD_VERTEX;
+    if (err & kErrNaN) return PANDORA_ERR_NAN_WEIGHT;
+    if (err & (kErrNotTree | kErrOverflow)) return PANDORA_ERR_NOT_A_TREE;
+    if (err) return PANDORA_ERR_HIP;
+    return PANDORA_OK;
+}
+
+#define PD_TRY(expr)                                 \
+    do {                                             \
+        if ((expr) != hipSuccess) return PANDORA_ERR_HIP; \
+    } while (0)
+
+int ensure(Workspace& ws, size_t dev_bytes, size_t host_bytes) {
+    if (ws.bytes < dev_bytes) {
+        if (ws.dev) {
+            if (hipStreamSynchronize(ws.stream) != hipSuccess) return PANDORA_ERR_HIP;
+            (void)hipFree(ws.dev);
+            ws.dev = nullptr;
+            ws.bytes = 0;
+        }
+        if (hipMalloc(&ws.dev, dev_bytes) != hipSuccess) {
+            ws.dev = nullptr;
+            (void)hipGetLastError();
+            return PANDORA_ERR_OUT_OF_MEMORY;
+        }
+        ws.bytes = dev_bytes;
+        // look-back words must start cleared; kernels keep them cleared after.
+        if (hipMemset(ws.dev, 0, dev_bytes) != hipSuccess) return PANDORA_ERR_HIP;
+    }
+    if (ws.host_bytes < host_bytes) {
+        if (ws.host) (void)hipHostFree(ws.host);
+        ws.host = nullptr;
+        ws.host_bytes = 0;
+        if (hipHostMalloc(&ws.host, host_bytes, hipHostMallocDefault) != hipSuccess) {
+            ws.host = nullptr;
+            (void)hipGetLastError();
+            return PANDORA_ERR_OUT_OF_MEMORY;
+        }
+        ws.host_bytes = host_bytes;
+    }
+    return PANDORA_OK;
+}
+
+template <class T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+int read_ctrl(Workspace& ws, Control* dctrl, Control* hctrl, hipStream_t s) {
+    PD_TRY(hipMemcpyAsync(hctrl, dctrl, kCtrlReadback, hipMemcpyDeviceToHost, s));
+    PD_TRY(hipStreamSynchronize(s));
+    (void)ws;
+    return PANDORA_OK;
+}
+
+// The whole path for a forest described by host offsets voff[0..B].
+int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, const float* w,
+        int32_t* edge_parent, int32_t* vertex_parent, hipStream_t s) {
+    const int64_t N = voff[B];
+    const int64_t M = N - B;
+    Stats st;
+    if (M == 0) {   // only single-vertex trees: every vertex is a root
+        PD_TRY(launch_fill_i32(vertex_parent, N, -1, s));
+        PD_TRY(hipStreamSynchronize(s));
+        g_last = st;
+        return PANDORA_OK;
+    }
+    int dev = 0;
+    PD_TRY(hipGetDevice(&dev));
+    Workspace& ws = *workspace_for(dev, s);
+    std::lock_guard<std::mutex> lock(ws.mu);
+    const Layout L = make_layout(N, B);
+    const size_t host_bytes = sizeof(Control) + sizeof(int64_t) * (B + 1);
+    int rc = ensure(ws, L.total, host_bytes);
+    if (rc != PANDORA_OK) return rc;
+
+    void* d = ws.dev;
+    Control* ctrl = at<Control>(d, L.ctrl);
+    Control* hctrl = static_cast<Control*>(ws.host);
+    int64_t* hvoff = reinterpret_cast<int64_t*>(static_cast<char*>(ws.host) + sizeof(Control));
+    std::memcpy(hvoff, voff, sizeof(int64_t) * (B + 1));
+    int64_t* dvoff = at<int64_t>(d, L.voff);
+    PD_TRY(hipMemcpyAsync(dvoff, hvoff, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
+    const Forest forest{dvoff, B};
+
+    uint32_t* K[2] = {at<uint32_t>(d, L.K0), at<uint32_t>(d, L.K1)};
+    int32_t* V[2] = {at<int32_t>(d, L.V0), at<int32_t>(d, L.V1)};
+    uint64_t* LB[2] = {at<uint64_t>(d, L.lb0), at<uint64_t>(d, L.lb1)};
+    int32_t* perm = at<int32_t>(d, L.perm);
+    int32_t* ur = at<int32_t>(d, L.ur);
+    int32_t* vr = at<int32_t>(d, L.vr);
+    int32_t* minInc_all = at<int32_t>(d, L.minInc);
+    int32_t* label_all = at<int32_t>(d, L.label);
+    int32_t* svflat = at<int32_t>(d, L.svflat);
+    const int64_t lb_words = sort_tiles(M) * kRadix;
+
+    PD_TRY(launch_zero_control(ctrl, s));
+
+    // ---- 1. weight sort --------------------------------------------------------
+    {
+        SortHistArgs h{};
+        h.n = M;
+        h.hist_row = 0;
+        h.passes = 4;
+        h.w = w;
+        h.fill = minInc_all;        // level-0 minInc starts at +inf
+        h.fill_n = N;
+        h.lb_zero = LB[0];
+        h.lb_zero_words = lb_words;
+        h.ctrl = ctrl;
+        PD_TRY(launch_sort_hist(SRC_WEIGHT, h, s));
+        const uint32_t* kin = nullptr;
+        const int32_t* vin = nullptr;
+        for (int p = 0; p < 4; ++p) {
+            SortPassArgs a{};
+            a.n = M;
+            a.shift = kSortBits * p;
+            a.pass = p;
+            a.w = w;
+            a.keys_in = kin;
+            a.vals_in = vin;
+            a.keys_out = K[p & 1];
+            a.vals_out = (p == 3) ? perm : V[p & 1];
+            a.u = u;
+            a.v = v;
+            a.ur = ur;
+            a.vr = vr;
+            a.forest = forest;
+            a.lb = LB[p & 1];
+            a.lb_zero = LB[(p + 1) & 1];
+            a.lb_zero_words = lb_words;
+            a.ctrl = ctrl;
+            PD_TRY(launch_sort_pass(p == 0 ? SRC_WEIGHT : SRC_KEYS, p == 3 ? DST_EDGES : DST_KEYS, a, s));
+            kin = K[p & 1];
+            vin = V[p & 1];
+        }
+    }
+
+    // ---- 2. contraction levels --------------------------------------------------
+    int32_t* EA[3] = {at<int32_t>(d, L.EA[0]), at<int32_t>(d, L.EA[1]), at<int32_t>(d, L.EA[2])};
+    int32_t* EB[3] = {at<int32_t>(d, L.EB[0]), at<int32_t>(d, L.EB[1]), at<int32_t>(d, L.EB[2])};
+    const int32_t* eu = ur;
+    const int32_t* ev = vr;
+    const int32_t* er = nullptr;
+    int64_t m = M, n = N, off = 0;
+    int j = 0;
+    while (m > 0 && (m > kTailE || n > kTailV)) {
+        if (j >= L.Lmax) return PANDORA_ERR_NOT_A_TREE;
+        const bool l0 = j == 0;
+        int32_t** out = (j % 2 == 0) ? EA : EB;
+        LevelArgs a{};
+        a.m = (int32_t)m;
+        a.n = (int32_t)n;
+        a.eu = eu;
+        a.ev = ev;
+        a.er = er;
+        a.minInc = minInc_all + off;
+        a.label = label_all + off;
+        a.minInc_next = minInc_all + off + n;
+        a.off_next = off + n;
+        a.ptr = at<int32_t>(d, L.ptr);
+        a.alpha = at<uint8_t>(d, L.alpha);
+        a.scan_lb = at<uint64_t>(d, L.scan_lb);
+        a.tile_alpha_excl = at<int32_t>(d, L.tile_excl);
+        a.out_u = out[0];
+        a.out_v = out[1];
+        a.out_r = out[2];
+        a.cap_next_e = (int32_t)L.capE[j + 1];
+        a.cap_next_v = (int32_t)L.capV[j + 1];
+        a.svflat = svflat;
+        a.perm = perm;
+        a.vertex_parent = vertex_parent;
+        a.forest = forest;
+        a.ctrl = ctrl;
+        a.jump_steps = kJumpSteps;
+        PD_TRY(launch_min_incident(l0, a, s));
+        PD_TRY(launch_alpha_hook(l0, a, s));
+        for (int round = 0;; ++round) {
+            if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
+            a.round = round;
+            PD_TRY(launch_jump(l0, a, s));
+            ++st.jump_launches;
+            rc = read_ctrl(ws, ctrl, hctrl, s);
+            if (rc != PANDORA_OK) return rc;
+            if (hctrl->err) return status_from_err(hctrl->err);
+            if (!(hctrl->not_converged & (1u << (round & 31)))) break;
+        }
+        const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
+        if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
+            return PANDORA_ERR_NOT_A_TREE;
+        PD_TRY(launch_compact(l0, a, s));
+        st.sum_edges += m;
+        ++st.levels;
+        off += n;
+        n = n_next;
+        m = m_next;
+        eu = out[0];
+        ev = out[1];
+        er = out[2];
+        ++j;
+    }
+
+    // ---- 3. remaining levels in LDS -------------------------------------------------
+    {
+        TailArgs t{};
+        t.m = (int32_t)m;
+        t.n = (int32_t)n;
+        t.eu = eu;
+        t.ev = ev;
+        t.er = er;
+        t.off = off;
+        t.flat_cap = L.flat_cap;
+        t.minInc_all = minInc_all;
+        t.label_all = label_all;
+        t.svflat = svflat;
+        t.perm = perm;
+        t.vertex_parent = vertex_parent;
+        t.forest = forest;
+        t.ctrl = ctrl;
+        st.tail_entry_edges = m;
+        st.sum_edges += m;
+        PD_TRY(launch_tail(t, s));
+    }
+
+    // ---- 4. expansion -----------------------------------------------------------------
+    {
+        WalkArgs wa{};
+        wa.m = M;
+        wa.n0 = N;
+        wa.flat_cap = L.flat_cap;
+        wa.svflat = svflat;
+        wa.minInc_all = minInc_all;
+        wa.label_all = label_all;
+        wa.ckey = K[0];
+        wa.hist_row = 4;
+        wa.passes = L.chain_passes;
+        wa.lb_zero = LB[0];
+        wa.lb_zero_words = lb_words;
+        wa.ctrl = ctrl;
+        PD_TRY(launch_walk_hist(wa, s));
+        const uint32_t* kin = K[0];
+        const int32_t* vin = perm;
+        for (int p = 0; p < L.chain_passes; ++p) {
+            SortPassArgs a{};
+            a.n = M;
+            a.shift = kSortBits * p;
+            a.pass = 4 + p;
+            a.keys_in = kin;
+            a.vals_in = vin;
+            a.keys_out = K[(p + 1) & 1];
+            a.vals_out = V[(p + 1) & 1];
+            a.forest = forest;
+            a.lb = LB[p & 1];
+            a.lb_zero = LB[(p + 1) & 1];
+            a.lb_zero_words = lb_words;
+            a.ctrl = ctrl;
+            PD_TRY(launch_sort_pass(SRC_KEYS, DST_KEYS, a, s));
+            kin = K[(p + 1) & 1];
+            vin = V[(p + 1) & 1];
+        }
+        StitchArgs sa{};
+        sa.m = M;
+        sa.n0 = N;
+        sa.flat_cap = L.flat_cap;
+        sa.skey = kin;
+        sa.sid = vin;
+        sa.minInc_all = minInc_all;
+        sa.perm = perm;
+        sa.edge_parent = edge_parent;
+        sa.forest = forest;
+        PD_TRY(launch_stitch(sa, s));
+    }
+    rc = read_ctrl(ws, ctrl, hctrl, s);
+    if (rc != PANDORA_OK) return rc;
+    if (hctrl->err) return status_from_err(hctrl->err);
+    if ((int64_t)hctrl->isolated != B) return PANDORA_ERR_NOT_A_TREE;
+    st.tail_levels = hctrl->tail_levels;
+    st.levels += hctrl->tail_levels;
+    g_last = st;
+    return PANDORA_OK;
+}
+
+}  // namespace
+}  // namespace pandora
+
+using namespace pandora;
+
+extern "C" {
+
+int pandora_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                       int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream) {
+    if (n < 1 || n > INT32_MAX || !vertex_parent) return PANDORA_ERR_INVALID_ARG;
+    if (n > 1 && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    const int64_t voff[2] = {0, n};
+    return run(voff, 1, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
+}
+
+int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
+                               const float* w, int32_t* edge_parent, int32_t* vertex_parent,
+                               void* hip_stream) {
+    if (B < 1 || !voff || !vertex_parent || voff[0] != 0) return PANDORA_ERR_INVALID_ARG;
+    for (int32_t b = 0; b < B; ++b)
+        if (voff[b + 1] <= voff[b]) return PANDORA_ERR_INVALID_ARG;
+    if (voff[B] > INT32_MAX) return PANDORA_ERR_INVALID_ARG;
+    if (voff[B] > B && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    return run(voff, B, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
+}
+
+size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B) {
+    if (B < 1 || n_total_vertices < B || n_total_vertices > INT32_MAX) return 0;
+    if (n_total_vertices == B) return 0;
+    return make_layout(n_total_vertices, B).total;
+}
+
+int pandora_last_stats(int64_t* out, int cap) {
+    const int64_t vals[5] = {g_last.levels, g_last.sum_edges, g_last.jump_launches, g_last.tail_levels,
+                             g_last.tail_entry_edges};
+    int k = 0;
+    for (; k < cap && k < 5; ++k) out[k] = vals[k];
+    return k;
+}
+
+void pandora_release_workspaces(void) {
+    std::lock_guard<std::mutex> g(g_mu);
+    for (auto& kv : g_ws) {
+        Workspace& ws = *kv.second;
+        std::lock_guard<std::mutex> l(ws.mu);
+        if (ws.dev) {
+            (void)hipStreamSynchronize(ws.stream);
+            (void)hipFree(ws.dev);
+        }
+        if (ws.host) (void)hipHostFree(ws.host);
+        ws.dev = nullptr;
+        ws.host = nullptr;
+        ws.bytes = ws.host_bytes = 0;
+    }
+    g_ws.clear();
+}
+
+const char* pandora_status_string(int status) {
+    switch (status) {
+        case PANDORA_OK: return "ok";
+        case PANDORA_ERR_INVALID_ARG: return "invalid argument";
+        case PANDORA_ERR_NOT_A_TREE: return "input is not a tree (cycle or disconnected)";
+        case PANDORA_ERR_NAN_WEIGHT: return "NaN edge weight";
+        case PANDORA_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case PANDORA_ERR_HIP: return "HIP runtime error";
+        case PANDORA_ERR_BAD_VERTEX: return "vertex id out of range";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,260 @@
+// Stable LSD radix sort with 8-bit digits for gfx950.
+//
+// Sorting is the first step of the method (the paper's Section 3.1.1 orders
+// the MST edges by weight with a consistent tie order) and it is used again
+// to group edges by dendrogram chain (Section 3.3.3).  The paper leaves the
+// sort to a library; here it is a one-sweep radix sort:
+//
+//   * one histogram pass computes the digit counts of every pass at once;
+//   * each digit pass loads a 4096-key tile, ranks it stably inside LDS
+//     (wave64 ballot matching of digits, per-wave digit counters), publishes
+//     the tile's per-digit counts and resolves the global offsets with a
+//     decoupled look-back over earlier tiles (dynamic tile ids, so every tile
+//     waited on has already started), then scatters from LDS in digit order
+//     so that runs of equal digits reach HBM as contiguous writes.
+//
+// Keys of the first sort are the monotone u32 image of the fp32 weights
+// (the value carried is the edge id, generated rather than read); the last
+// pass of that sort writes the rank->edge permutation and gathers the two
+// endpoints of each edge into rank order, translating tree-local ids of a
+// batched forest into global ids and validating them on the way.
+#include "kernels.hpp"
+
+namespace pandora {
+
+namespace {
+
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagInc = 2ull << 62;
+constexpr uint64_t kFlagMask = 3ull << 62;
+constexpr uint64_t kCountMask = ~kFlagMask;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+static_assert(kRadix == kSortBlock, "one digit per thread");
+
+// Exclusive scan of one value per thread across a block of BLOCK threads.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wsum) {
+    constexpr int W = BLOCK / kWave;
+    const int wave = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane_id() == kWave - 1) s_wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        if (w < wave) before += s_wsum[w];
+    __syncthreads();
+    return before + inc - x;
+}
+
+template <int SRC>
+__global__ __launch_bounds__(256) void k_sort_hist(SortHistArgs a) {
+    __shared__ uint32_t s_h[4][kRadix];
+    for (int i = threadIdx.x; i < 4 * kRadix; i += blockDim.x) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool nan_seen = false;
+    for (int64_t i = t0; i < a.n; i += stride) {
+        uint32_t key;
+        if (SRC == SRC_WEIGHT) {
+            const float w = a.w[i];
+            nan_seen |= is_nan_bits(w);
+            key = weight_key(w);
+        } else {
+            key = a.keys[i];
+        }
+        for (int p = 0; p < a.passes; ++p)
+            atomicAdd(&s_h[p][(key >> (kSortBits * p)) & (kRadix - 1)], 1u);
+    }
+    for (int64_t i = t0; i < a.fill_n; i += stride) a.fill[i] = kInf;
+    for (int64_t i = t0; i < a.lb_zero_words; i += stride) a.lb_zero[i] = 0;
+    if (SRC == SRC_WEIGHT && ballot(nan_seen) != 0 && lane_id() == 0) raise_err(a.ctrl, kErrNaN);
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.passes * kRadix; i += blockDim.x) {
+        const uint32_t c = (&s_h[0][0])[i];
+        if (c) atomicAdd(&a.ctrl->hist[a.hist_row + i / kRadix][i % kRadix], c);
+    }
+}
+
+template <int SRC, int DST>
+__global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
+    constexpr int W = kSortBlock / kWave;
+    __shared__ uint32_t s_cnt[W][kRadix];     // per-wave digit counters, then offsets
+    __shared__ uint32_t s_start[kRadix];      // first local slot of each digit
+    __shared__ int64_t s_gbase[kRadix];       // global slot of local slot 0 per digit
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ int32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wsum[W];
+    __shared__ uint32_t s_tile;
+
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    const int lane = lane_id();
+
+    {   // clear the next pass's look-back words (that buffer was used two passes ago)
+        const int64_t stride = (int64_t)gridDim.x * kSortBlock;
+        for (int64_t i = (int64_t)blockIdx.x * kSortBlock + tid; i < a.lb_zero_words; i += stride)
+            a.lb_zero[i] = 0;
+    }
+    for (int i = tid; i < W * kRadix; i += kSortBlock) (&s_cnt[0][0])[i] = 0;
+    if (tid == 0) s_tile = atomicAdd(&a.ctrl->sort_tiles[a.pass], 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * kSortTile;
+    const int64_t wbase = base + (int64_t)wave * (kWave * kSortItems);
+
+    uint32_t key[kSortItems];
+    int32_t val[kSortItems];
+    uint32_t rank[kSortItems];
+
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t idx = wbase + k * kWave + lane;
+        key[k] = 0xffffffffu;
+        val[k] = -1;
+        if (idx < a.n) {
+            if (SRC == SRC_WEIGHT) {
+                key[k] = weight_key(a.w[idx]);
+                val[k] = (int32_t)idx;
+            } else {
+                key[k] = a.keys_in[idx];
+                val[k] = a.vals_in[idx];
+            }
+        }
+    }
+
+    // Stable in-wave ranking: lanes holding the same digit find each other with
+    // one ballot per digit bit; the lowest such lane bumps the wave's counter.
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const bool valid = wbase + k * kWave + lane < a.n;
+        const uint32_t d = (key[k] >> a.shift) & (kRadix - 1);
+        uint64_t peers = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kSortBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t mb = ballot(bit);
+            peers &= bit ? mb : ~mb;
+        }
+        rank[k] = 0;
+        if (valid) {
+            const uint64_t below = peers & lanemask_lt();
+            const uint32_t c = s_cnt[wave][d];
+            rank[k] = c + (uint32_t)popc64(below);
+            if (below == 0) s_cnt[wave][d] = c + (uint32_t)popc64(peers);
+        }
+    }
+    __syncthreads();
+
+    // Thread d owns digit d: wave offsets, tile total, look-back.
+    const int d = tid;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t c = s_cnt[w][d];
+        s_cnt[w][d] = tot;
+        tot += c;
+    }
+    uint64_t* my = a.lb + tile * kRadix + d;
+    st_relaxed(my, (tile == 0 ? kFlagInc : kFlagAgg) | (uint64_t)tot);
+
+    const uint32_t hist_d = a.ctrl->hist[a.pass][d];
+    const uint32_t digit_off = block_excl_scan<kSortBlock>(hist_d, s_wsum);
+    const uint32_t start = block_excl_scan<kSortBlock>(tot, s_wsum);
+    s_start[d] = start;
+
+    uint64_t excl = 0;
+    if (tile > 0) {
+        int64_t p = tile - 1;
+        uint32_t spins = 0;
+        while (true) {
+            const uint64_t wv = ld_relaxed(a.lb + p * kRadix + d);
+            const uint64_t flag = wv & kFlagMask;
+            if (flag == 0) {
+                if (++spins > kSpinLimit) {
+                    raise_err(a.ctrl, kErrSpin);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            spins = 0;
+            excl += wv & kCountMask;
+            if (flag == kFlagInc || p == 0) break;
+            --p;
+        }
+        st_relaxed(my, kFlagInc | (excl + tot));
+    }
+    s_gbase[d] = (int64_t)digit_off + (int64_t)excl - (int64_t)start;
+    __syncthreads();
+
+    // Place the tile in digit order in LDS.
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        if (wbase + k * kWave + lane < a.n) {
+            const uint32_t dd = (key[k] >> a.shift) & (kRadix - 1);
+            const uint32_t lp = s_start[dd] + s_cnt[wave][dd] + rank[k];
+            s_keys[lp] = key[k];
+            s_vals[lp] = val[k];
+        }
+    }
+    __syncthreads();
+
+    // Scatter: consecutive threads take consecutive LDS slots, so each digit's
+    // run lands on consecutive global slots.
+    const int tile_n = (int)((a.n - base) < kSortTile ? (a.n - base) : kSortTile);
+    bool bad = false;
+    for (int i = tid; i < tile_n; i += kSortBlock) {
+        const uint32_t kk = s_keys[i];
+        const int64_t g = s_gbase[(kk >> a.shift) & (kRadix - 1)] + i;
+        const int32_t id = s_vals[i];
+        // Only reachable after a look-back failure (already reported): never
+        // write or gather outside the arrays.
+        if (g < 0 || g >= a.n || (DST == DST_EDGES && (id < 0 || id >= a.n))) continue;
+        if (DST == DST_KEYS) {
+            a.keys_out[g] = kk;
+            a.vals_out[g] = id;
+        } else {
+            a.vals_out[g] = id;
+            const int32_t b = a.forest.tree_of_edge(id);
+            const int64_t v0 = a.forest.voff[b];
+            const int64_t nb = a.forest.voff[b + 1] - v0;
+            int64_t x = a.u[id];
+            int64_t y = a.v[id];
+            if (x < 0 || x >= nb) { bad = true; x = 0; }
+            if (y < 0 || y >= nb) { bad = true; y = 0; }
+            a.ur[g] = (int32_t)(v0 + x);
+            a.vr[g] = (int32_t)(v0 + y);
+        }
+    }
+    if (DST == DST_EDGES && ballot(bad) != 0 && lane == 0) raise_err(a.ctrl, kErrBadVertex);
+}
+
+}  // namespace
+
+hipError_t launch_sort_hist(int src, const SortHistArgs& a, hipStream_t s) {
+    const int64_t work = a.n > a.fill_n ? a.n : a.fill_n;
+    int64_t blocks = (work + 256 * 16 - 1) / (256 * 16);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    if (src == SRC_WEIGHT)
+        k_sort_hist<SRC_WEIGHT><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a);
+    else
+        k_sort_hist<SRC_KEYS><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_pass(int src, int dst, const SortPassArgs& a, hipStream_t s) {
+    const int64_t tiles = sort_tiles(a.n);
+    if (tiles < 1) return hipSuccess;
+    const dim3 grid((unsigned)tiles), block(kSortBlock);
+    if (src == SRC_WEIGHT && dst == DST_KEYS) k_sort_pass<SRC_WEIGHT, DST_KEYS><<<grid, block, 0, s>>>(a);
+    else if (src == SRC_WEIGHT) k_sort_pass<SRC_WEIGHT, DST_EDGES><<<grid, block, 0, s>>>(a);
+    else if (dst == DST_KEYS) k_sort_pass<SRC_KEYS, DST_KEYS><<<grid, block, 0, s>>>(a);
+    else k_sort_pass<SRC_KEYS, DST_EDGES><<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace pandora
