@@ -93,6 +93,17 @@ size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B);
  * the level the LDS tail started from.  Returns the number filled (<= cap). */
 int pandora_last_stats(int64_t* out, int cap);
 
+/* Per-kernel profiler (tracing).  pandora_profile_enable(mask) clears the
+ * counters and, for every kernel kind k with bit k set in mask, brackets each
+ * launch with a pair of HIP events on the call's stream; mask 0 turns it
+ * off.  pandora_profile_read fills, per kind, the summed event time in ms,
+ * the summed algorithmic bytes (the minimum traffic of each launch) and the
+ * launch count; it returns the number of kinds (<= cap).  Kind names come
+ * from pandora_profile_name.  Counters are process-wide. */
+int pandora_profile_enable(uint32_t kind_mask);
+int pandora_profile_read(double* ms, double* bytes, int64_t* launches, int cap);
+const char* pandora_profile_name(int kind);
+
 /* Free every cached scratch allocation (waits for the owning streams). */
 void pandora_release_workspaces(void);
 

@@ -57,6 +57,13 @@ def _load():
     lib.pandora_last_stats.restype = ctypes.c_int
     lib.pandora_release_workspaces.argtypes = []
     lib.pandora_release_workspaces.restype = None
+    lib.pandora_profile_enable.argtypes = [ctypes.c_uint32]
+    lib.pandora_profile_enable.restype = ctypes.c_int
+    lib.pandora_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.pandora_profile_read.restype = ctypes.c_int
+    lib.pandora_profile_name.argtypes = [ctypes.c_int]
+    lib.pandora_profile_name.restype = ctypes.c_char_p
     lib.pandora_status_string.argtypes = [ctypes.c_int]
     lib.pandora_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -166,3 +173,24 @@ def last_stats() -> dict:
 
 def release_workspaces():
     _load().pandora_release_workspaces()
+
+
+PROFILE_ALL = 0xFFFFFFFF
+
+
+def profile_enable(mask: int = PROFILE_ALL) -> None:
+    """Clear the per-kernel profiler and time the kernel kinds in `mask`
+    (bit k = kind k; 0 turns profiling off)."""
+    _load().pandora_profile_enable(int(mask) & 0xFFFFFFFF)
+
+
+def profile_read() -> dict:
+    """{kind name: {"ms", "bytes", "launches"}} accumulated since profile_enable."""
+    lib = _load()
+    cap = 32
+    ms = (ctypes.c_double * cap)()
+    by = (ctypes.c_double * cap)()
+    ln = (ctypes.c_int64 * cap)()
+    k = lib.pandora_profile_read(ms, by, ln, cap)
+    return {lib.pandora_profile_name(i).decode(): {"kind": i, "ms": ms[i], "bytes": by[i], "launches": int(ln[i])}
+            for i in range(k)}

@@ -127,6 +127,83 @@ struct Stats {
 };
 thread_local Stats g_last;
 
+// ---- per-kernel profiler: HIP events around selected launches -------------------
+// Algorithmic bytes per launch are the minimum traffic of each kernel (every
+// array element it must read or write once; gathers count 4 bytes).
+enum ProfKind {
+    PK_ZERO, PK_SORT_HIST, PK_SORT_W_FIRST, PK_SORT_W_MID, PK_SORT_W_LAST, PK_MIN_INC,
+    PK_ALPHA_HOOK, PK_JUMP, PK_COMPACT, PK_TAIL, PK_WALK_HIST, PK_SORT_C_PASS, PK_STITCH,
+    PK_COUNT
+};
+const char* const kProfNames[PK_COUNT] = {
+    "zero_control", "sort_hist", "sort_pass_weight_first", "sort_pass_weight_mid",
+    "sort_pass_weight_last", "min_incident", "alpha_hook", "jump", "compact", "tail",
+    "walk_hist", "sort_pass_chain", "stitch"};
+
+struct Prof {
+    std::mutex mu;
+    uint32_t mask = 0;                // kinds being timed (0 = profiling off)
+    double ms[PK_COUNT] = {};
+    double bytes[PK_COUNT] = {};
+    int64_t launches[PK_COUNT] = {};
+};
+Prof g_prof;
+
+struct PendingEvent {
+    hipEvent_t a, b;
+    int kind;
+    double bytes;
+};
+thread_local std::vector<PendingEvent> t_pending;
+thread_local std::vector<hipEvent_t> t_event_pool;
+
+hipEvent_t pooled_event() {
+    if (!t_event_pool.empty()) {
+        hipEvent_t e = t_event_pool.back();
+        t_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <class F>
+hipError_t timed(int kind, double bytes, hipStream_t s, F&& launch) {
+    uint32_t mask;
+    {
+        std::lock_guard<std::mutex> g(g_prof.mu);
+        mask = g_prof.mask;
+    }
+    if (!(mask & (1u << kind))) return launch();
+    hipEvent_t a = pooled_event(), b = pooled_event();
+    if (!a || !b) return launch();
+    (void)hipEventRecord(a, s);
+    const hipError_t e = launch();
+    (void)hipEventRecord(b, s);
+    t_pending.push_back({a, b, kind, bytes});
+    return e;
+}
+
+// Called once the stream has been synchronized.
+void drain_profile() {
+    if (t_pending.empty()) return;
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    for (const PendingEvent& p : t_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g_prof.ms[p.kind] += ms;
+            g_prof.bytes[p.kind] += p.bytes;
+            g_prof.launches[p.kind] += 1;
+        }
+        t_event_pool.push_back(p.a);
+        t_event_pool.push_back(p.b);
+    }
+    t_pending.clear();
+}
+
+#define PD_TIMED(kind, bytes, expr) PD_TRY(timed((kind), (double)(bytes), s, [&]() { return (expr); }))
+
 Workspace* workspace_for(int dev, hipStream_t s) {
     std::lock_guard<std::mutex> g(g_mu);
     auto& slot = g_ws[{dev, s}];
@@ -234,7 +311,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     int32_t* svflat = at<int32_t>(d, L.svflat);
     const int64_t lb_words = sort_tiles(M) * kRadix;
 
-    PD_TRY(launch_zero_control(ctrl, s));
+    PD_TIMED(PK_ZERO, sizeof(Control), launch_zero_control(ctrl, s));
 
     // ---- 1. weight sort --------------------------------------------------------
     {
@@ -248,7 +325,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         h.lb_zero = LB[0];
         h.lb_zero_words = lb_words;
         h.ctrl = ctrl;
-        PD_TRY(launch_sort_hist(SRC_WEIGHT, h, s));
+        PD_TIMED(PK_SORT_HIST, 4.0 * M + 4.0 * N, launch_sort_hist(SRC_WEIGHT, h, s));
         const uint32_t* kin = nullptr;
         const int32_t* vin = nullptr;
         for (int p = 0; p < 4; ++p) {
@@ -270,7 +347,9 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
             a.lb_zero = LB[(p + 1) & 1];
             a.lb_zero_words = lb_words;
             a.ctrl = ctrl;
-            PD_TRY(launch_sort_pass(p == 0 ? SRC_WEIGHT : SRC_KEYS, p == 3 ? DST_EDGES : DST_KEYS, a, s));
+            const int kind = p == 0 ? PK_SORT_W_FIRST : (p == 3 ? PK_SORT_W_LAST : PK_SORT_W_MID);
+            const double by = (p == 0 ? 12.0 : (p == 3 ? 28.0 : 16.0)) * M;
+            PD_TIMED(kind, by, launch_sort_pass(p == 0 ? SRC_WEIGHT : SRC_KEYS, p == 3 ? DST_EDGES : DST_KEYS, a, s));
             kin = K[p & 1];
             vin = V[p & 1];
         }
@@ -313,12 +392,12 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         a.forest = forest;
         a.ctrl = ctrl;
         a.jump_steps = kJumpSteps;
-        PD_TRY(launch_min_incident(l0, a, s));
-        PD_TRY(launch_alpha_hook(l0, a, s));
+        PD_TIMED(PK_MIN_INC, (l0 ? 16.0 : 20.0) * m + 4.0 * n, launch_min_incident(l0, a, s));
+        PD_TIMED(PK_ALPHA_HOOK, (l0 ? 17.0 : 21.0) * m + 4.0 * n, launch_alpha_hook(l0, a, s));
         for (int round = 0;; ++round) {
             if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
             a.round = round;
-            PD_TRY(launch_jump(l0, a, s));
+            PD_TIMED(PK_JUMP, (round == 0 ? (l0 ? 32.0 : 24.0) : 20.0) * n, launch_jump(l0, a, s));
             ++st.jump_launches;
             rc = read_ctrl(ws, ctrl, hctrl, s);
             if (rc != PANDORA_OK) return rc;
@@ -328,7 +407,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
         if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
             return PANDORA_ERR_NOT_A_TREE;
-        PD_TRY(launch_compact(l0, a, s));
+        PD_TIMED(PK_COMPACT, (l0 ? 13.0 : 17.0) * m + 16.0 * m_next, launch_compact(l0, a, s));
         st.sum_edges += m;
         ++st.levels;
         off += n;
@@ -359,7 +438,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         t.ctrl = ctrl;
         st.tail_entry_edges = m;
         st.sum_edges += m;
-        PD_TRY(launch_tail(t, s));
+        PD_TIMED(PK_TAIL, 12.0 * m, launch_tail(t, s));
     }
 
     // ---- 4. expansion -----------------------------------------------------------------
@@ -377,7 +456,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         wa.lb_zero = LB[0];
         wa.lb_zero_words = lb_words;
         wa.ctrl = ctrl;
-        PD_TRY(launch_walk_hist(wa, s));
+        PD_TIMED(PK_WALK_HIST, 12.0 * M, launch_walk_hist(wa, s));
         const uint32_t* kin = K[0];
         const int32_t* vin = perm;
         for (int p = 0; p < L.chain_passes; ++p) {
@@ -394,7 +473,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
             a.lb_zero = LB[(p + 1) & 1];
             a.lb_zero_words = lb_words;
             a.ctrl = ctrl;
-            PD_TRY(launch_sort_pass(SRC_KEYS, DST_KEYS, a, s));
+            PD_TIMED(PK_SORT_C_PASS, 16.0 * M, launch_sort_pass(SRC_KEYS, DST_KEYS, a, s));
             kin = K[(p + 1) & 1];
             vin = V[(p + 1) & 1];
         }
@@ -408,7 +487,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         sa.perm = perm;
         sa.edge_parent = edge_parent;
         sa.forest = forest;
-        PD_TRY(launch_stitch(sa, s));
+        PD_TIMED(PK_STITCH, 12.0 * M, launch_stitch(sa, s));
     }
     rc = read_ctrl(ws, ctrl, hctrl, s);
     if (rc != PANDORA_OK) return rc;
@@ -418,6 +497,16 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     st.levels += hctrl->tail_levels;
     g_last = st;
     return PANDORA_OK;
+}
+
+int run_and_drain(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, const float* w,
+                  int32_t* edge_parent, int32_t* vertex_parent, hipStream_t s) {
+    const int rc = run(voff, B, u, v, w, edge_parent, vertex_parent, s);
+    if (!t_pending.empty()) {
+        (void)hipStreamSynchronize(s);
+        drain_profile();
+    }
+    return rc;
 }
 
 }  // namespace
@@ -432,7 +521,7 @@ int pandora_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const floa
     if (n < 1 || n > INT32_MAX || !vertex_parent) return PANDORA_ERR_INVALID_ARG;
     if (n > 1 && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
     const int64_t voff[2] = {0, n};
-    return run(voff, 1, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
+    return run_and_drain(voff, 1, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
 }
 
 int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
@@ -443,7 +532,7 @@ int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u,
         if (voff[b + 1] <= voff[b]) return PANDORA_ERR_INVALID_ARG;
     if (voff[B] > INT32_MAX) return PANDORA_ERR_INVALID_ARG;
     if (voff[B] > B && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
-    return run(voff, B, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
+    return run_and_drain(voff, B, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
 }
 
 size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B) {
@@ -458,6 +547,32 @@ int pandora_last_stats(int64_t* out, int cap) {
     int k = 0;
     for (; k < cap && k < 5; ++k) out[k] = vals[k];
     return k;
+}
+
+int pandora_profile_enable(uint32_t kind_mask) {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    g_prof.mask = kind_mask;
+    for (int k = 0; k < PK_COUNT; ++k) {
+        g_prof.ms[k] = 0;
+        g_prof.bytes[k] = 0;
+        g_prof.launches[k] = 0;
+    }
+    return PK_COUNT;
+}
+
+int pandora_profile_read(double* ms, double* bytes, int64_t* launches, int cap) {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    int k = 0;
+    for (; k < cap && k < PK_COUNT; ++k) {
+        if (ms) ms[k] = g_prof.ms[k];
+        if (bytes) bytes[k] = g_prof.bytes[k];
+        if (launches) launches[k] = g_prof.launches[k];
+    }
+    return k;
+}
+
+const char* pandora_profile_name(int kind) {
+    return (kind >= 0 && kind < PK_COUNT) ? kProfNames[kind] : "";
 }
 
 void pandora_release_workspaces(void) {
