@@ -38,6 +38,9 @@ WORKLOADS = {
     "c3": "preferential-attachment tree, n=50,000,000, lognormal(0,1.5) fp32 weights, 5% x10 bridges",
     "c4": "4,096 trees, lognormal sizes in [100, 1,000,000] (~50M edges), half random-recursive "
           "half caterpillar, fp32 uniform weights, one batched call",
+    "c5": "serving: Poisson arrivals at 2,000 req/s of random recursive trees with log-uniform "
+          "sizes in [1,000, 10,000,000] and lognormal(0,1.5) fp32 weights, drawn from a "
+          "device-resident pool, admitted by HBM footprint against a 200 GB budget",
 }
 
 
@@ -81,6 +84,17 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="also report every kernel kind's time")
+    ap.add_argument("--compare-per-tree", action="store_true",
+                    help="c4: also time the same trees built one call per tree")
+    ap.add_argument("--duration", type=float, default=20.0, help="c5: seconds of arrivals")
+    ap.add_argument("--discard", type=float, default=5.0, help="c5: warm-up seconds not reported")
+    ap.add_argument("--rate", type=float, default=2000.0, help="c5: arrivals per second")
+    ap.add_argument("--pool", type=int, default=96, help="c5: distinct trees in the device pool")
+    ap.add_argument("--streams", type=int, default=4, help="c5: server worker streams")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="c5: admission budget")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy: a kernel of known traffic "
+                         "for scaling hardware byte counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -96,6 +110,16 @@ def main():
     pd.library()   # fails loudly if the HIP library is not built
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.calibrate_copy:
+        src = torch.ones(256 * 1024 * 1024, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    if args.workload == "c5":
+        return run_serving(args, dev)
 
     t0 = time.time()
     items = make_inputs(args.workload)
@@ -194,6 +218,30 @@ def main():
                              "GBps": (s["bytes"] / (s["ms"] / 1000) / 1e9) if s["ms"] > 0 else None}
                          for k, s in stages.items() if s["launches"]}
 
+    if args.compare_per_tree and args.workload == "c4":
+        f = items[0][1]
+        trees = []
+        for b in range(f.B):
+            v0, v1 = int(f.voff[b]), int(f.voff[b + 1])
+            e0, e1 = v0 - b, v1 - b - 1
+            u, v, w = calls[0][2][e0:e1], calls[0][3][e0:e1], calls[0][4][e0:e1]
+            trees.append((v1 - v0, u, v, w, torch.empty(max(e1 - e0, 0), dtype=torch.int32, device=dev),
+                          torch.empty(v1 - v0, dtype=torch.int32, device=dev)))
+
+        def per_tree():
+            for t in trees:
+                st = pd.dendrogram_into(*t)
+                if st != pd.OK:
+                    raise RuntimeError(pd.status_string(st))
+        per_tree()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        per_tree()
+        torch.cuda.synchronize()
+        per_s = time.perf_counter() - a
+        out["per_tree_calls"] = {"seconds": per_s, "edges_per_s": total_edges / per_s,
+                                 "batched_speedup": per_s / (ms_per_step / 1000.0), "calls": len(trees)}
+
     if not args.no_cpu_baseline:
         import oracle
         log("timing the CPU oracle on the same inputs ...")
@@ -210,6 +258,81 @@ def main():
                                          f"single-threaded sort + union-find sweep",
                                "seconds": cpu_s, "host_cpu": cpu_model(),
                                "host_threads_available": os.cpu_count()}
+    print(json.dumps(out), flush=True)
+
+
+def run_serving(args, dev):
+    """Open-loop serving run: Poisson arrivals, continuous batching, p50/p99 latency."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2401_06089_amd.serve import DendrogramServer, Request, latency_stats
+
+    rng_sizes = gen.uniform_f64(args.pool, 0, stream=11)
+    sizes = np.floor(np.exp(np.log(1e3) + rng_sizes * (np.log(1e7) - np.log(1e3)))).astype(np.int64)
+    t0 = time.time()
+    pool = []
+    for i, n in enumerate(sizes):
+        t = gen.rrt(int(n), gen.hash2(5, i), weights="lognormal")
+        pool.append((t.n, torch.from_numpy(t.u).to(dev), torch.from_numpy(t.v).to(dev),
+                     torch.from_numpy(t.w).to(dev)))
+    torch.cuda.synchronize()
+    log(f"pool of {len(pool)} trees ({int(sizes.sum() - len(sizes))} edges) in {time.time() - t0:.1f}s")
+
+    n_req = int(args.rate * args.duration * 1.2) + 16
+    gaps = -np.log(1.0 - gen.uniform_f64(n_req, 0, stream=12)) / args.rate
+    offsets = np.cumsum(gaps)
+    offsets = offsets[offsets < args.duration]
+    picks = (gen.uniform_f64(len(offsets), 0, stream=13) * len(pool)).astype(np.int64)
+
+    srv = DendrogramServer(int(args.budget_gb * 1e9), streams=args.streams)
+    # warm the library and every stream's scratch once before the clock starts
+    warm = [Request(-1 - k, *pool[int(np.argmax(sizes))], arrival=time.perf_counter())
+            for k in range(args.streams)]
+    for r in warm:
+        srv.submit(r)
+    for r in warm:
+        r.future.result()
+    srv.done.clear()
+
+    start = time.perf_counter()
+    reqs = []
+    for i, off in enumerate(offsets):
+        now = time.perf_counter()
+        due = start + off
+        if due > now:
+            time.sleep(due - now)
+        n, u, v, w = pool[int(picks[i])]
+        r = Request(i, n, u, v, w, arrival=due)
+        reqs.append(r)
+        srv.submit(r)
+    for r in reqs:
+        r.future.result()
+    end = time.perf_counter()
+    srv.close()
+    kept = [r for r in reqs if r.arrival - start >= args.discard]
+    span = max(r.finished for r in kept) - min(r.arrival for r in kept) if kept else 1.0
+    edges = sum(r.n - 1 for r in kept)
+    stats = latency_stats(reqs, args.discard, start)
+    out = {
+        "metric": "MST edges/sec -> dendrogram (serving)",
+        "value": edges / span,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "c5", "description": WORKLOADS["c5"], "rate_per_s": args.rate,
+                   "duration_s": args.duration, "discarded_s": args.discard, "pool_trees": len(pool),
+                   "streams": args.streams, "budget_bytes": srv.budget},
+        "latency_ms": {"p50": stats.get("p50_ms"), "p99": stats.get("p99_ms"),
+                       "mean": stats.get("mean_ms"), "max": stats.get("max_ms"), "per": "request"},
+        "requests": {"submitted": len(reqs), "measured": stats.get("count"),
+                     "offered_edges_per_s": float(sum(pool[int(p)][0] - 1 for p in picks) / args.duration),
+                     "batches": srv.batches, "max_concurrent_batches": srv.max_concurrent,
+                     "peak_admitted_bytes": srv.peak_in_use, "wall_s": end - start},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -130,15 +130,19 @@ thread_local Stats g_last;
 // ---- per-kernel profiler: HIP events around selected launches -------------------
 // Algorithmic bytes per launch are the minimum traffic of each kernel (every
 // array element it must read or write once; gathers count 4 bytes).
+// Level kernels are split into their level-0 and deeper-level instantiations
+// (different templates, different sizes per launch).
 enum ProfKind {
     PK_ZERO, PK_SORT_HIST, PK_SORT_W_FIRST, PK_SORT_W_MID, PK_SORT_W_LAST, PK_MIN_INC,
     PK_ALPHA_HOOK, PK_JUMP, PK_COMPACT, PK_TAIL, PK_WALK_HIST, PK_SORT_C_PASS, PK_STITCH,
+    PK_MIN_INC_N, PK_ALPHA_HOOK_N, PK_JUMP_N, PK_COMPACT_N,
     PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "zero_control", "sort_hist", "sort_pass_weight_first", "sort_pass_weight_mid",
-    "sort_pass_weight_last", "min_incident", "alpha_hook", "jump", "compact", "tail",
-    "walk_hist", "sort_pass_chain", "stitch"};
+    "sort_pass_weight_last", "min_incident_l0", "alpha_hook_l0", "jump_l0", "compact_l0", "tail",
+    "walk_hist", "sort_pass_chain", "stitch", "min_incident_ln", "alpha_hook_ln", "jump_ln",
+    "compact_ln"};
 
 struct Prof {
     std::mutex mu;
@@ -241,8 +245,10 @@ int ensure(Workspace& ws, size_t dev_bytes, size_t host_bytes) {
             return PANDORA_ERR_OUT_OF_MEMORY;
         }
         ws.bytes = dev_bytes;
-        // look-back words must start cleared; kernels keep them cleared after.
-        if (hipMemset(ws.dev, 0, dev_bytes) != hipSuccess) return PANDORA_ERR_HIP;
+        // No initial clearing: every look-back buffer is cleared on the call's
+        // stream by the kernel that runs before its first user.  (A blocking
+        // memset here would run on the null stream, unordered with respect to
+        // non-blocking streams that may already be computing.)
     }
     if (ws.host_bytes < host_bytes) {
         if (ws.host) (void)hipHostFree(ws.host);
@@ -392,12 +398,12 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         a.forest = forest;
         a.ctrl = ctrl;
         a.jump_steps = kJumpSteps;
-        PD_TIMED(PK_MIN_INC, (l0 ? 16.0 : 20.0) * m + 4.0 * n, launch_min_incident(l0, a, s));
-        PD_TIMED(PK_ALPHA_HOOK, (l0 ? 17.0 : 21.0) * m + 4.0 * n, launch_alpha_hook(l0, a, s));
+        PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 16.0 : 20.0) * m + 4.0 * n, launch_min_incident(l0, a, s));
+        PD_TIMED(l0 ? PK_ALPHA_HOOK : PK_ALPHA_HOOK_N, (l0 ? 17.0 : 21.0) * m + 4.0 * n, launch_alpha_hook(l0, a, s));
         for (int round = 0;; ++round) {
             if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
             a.round = round;
-            PD_TIMED(PK_JUMP, (round == 0 ? (l0 ? 32.0 : 24.0) : 20.0) * n, launch_jump(l0, a, s));
+            PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? (l0 ? 32.0 : 24.0) : 20.0) * n, launch_jump(l0, a, s));
             ++st.jump_launches;
             rc = read_ctrl(ws, ctrl, hctrl, s);
             if (rc != PANDORA_OK) return rc;
@@ -407,7 +413,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
         if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
             return PANDORA_ERR_NOT_A_TREE;
-        PD_TIMED(PK_COMPACT, (l0 ? 13.0 : 17.0) * m + 16.0 * m_next, launch_compact(l0, a, s));
+        PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, (l0 ? 13.0 : 17.0) * m + 16.0 * m_next, launch_compact(l0, a, s));
         st.sum_edges += m;
         ++st.levels;
         off += n;

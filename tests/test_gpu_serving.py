@@ -1,0 +1,74 @@
+"""Continuous-batching server: every request's dendrogram is the same as when it
+is built alone, the byte budget is never exceeded, and batches overlap."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2401_06089_amd as pd
+    pd.library()
+    yield
+
+
+def test_server_results_match_alone_and_budget_holds():
+    import paper_2401_06089_amd as pd
+    from paper_2401_06089_amd.serve import DendrogramServer, Request, request_footprint
+
+    dev = torch.device("cuda:0")
+    sizes = np.floor(np.exp(np.log(1e3) + gen.uniform_f64(24, 7, 30) * (np.log(3e5) - np.log(1e3))))
+    pool = []
+    for i, n in enumerate(sizes.astype(np.int64)):
+        t = gen.rrt(int(n), 100 + i, weights="lognormal") if i % 2 else gen.caterpillar(int(n), None, 1e-3, i)
+        pool.append((t, tuple(torch.from_numpy(a).to(dev) for a in (t.u, t.v, t.w))))
+    alone = []
+    for t, (u, v, w) in pool:
+        ep, vp = pd.dendrogram(u, v, w, n=t.n)
+        alone.append((ep.cpu().numpy(), vp.cpu().numpy()))
+    for k in (0, 5, 11):
+        oep, ovp = oracle.dendrogram(pool[k][0].n, pool[k][0].u, pool[k][0].v, pool[k][0].w)
+        assert np.array_equal(alone[k][0], oep) and np.array_equal(alone[k][1], ovp)
+
+    budget = 3 * max(request_footprint(int(n)) for n in sizes)   # forces admission waits
+    srv = DendrogramServer(budget, streams=3, max_batch_edges=600_000)
+    picks = (gen.uniform_f64(160, 8, 31) * len(pool)).astype(np.int64)
+    reqs = []
+    t0 = time.perf_counter()
+    for i, p in enumerate(picks):
+        t, (u, v, w) = pool[int(p)]
+        r = Request(i, t.n, u, v, w, arrival=time.perf_counter())
+        reqs.append((int(p), r))
+        srv.submit(r)
+        if i % 40 == 39:
+            time.sleep(0.002)
+    for p, r in reqs:
+        ep, vp = r.future.result(timeout=120)
+        assert np.array_equal(ep.cpu().numpy(), alone[p][0]), f"request {r.rid} differs in the mix"
+        assert np.array_equal(vp.cpu().numpy(), alone[p][1])
+    srv.close()
+    assert srv.peak_in_use <= budget
+    assert srv.batches < len(reqs)            # requests were batched together
+    assert srv.max_concurrent >= 2            # batches ran side by side on different streams
+    assert time.perf_counter() - t0 < 120
+
+
+def test_server_rejects_oversized_request():
+    from paper_2401_06089_amd.serve import DendrogramServer, Request
+    t = gen.rrt(100_000, 1)
+    u, v, w = (torch.from_numpy(a).cuda() for a in (t.u, t.v, t.w))
+    srv = DendrogramServer(1 << 20, streams=1)
+    r = Request(0, t.n, u, v, w, arrival=time.perf_counter())
+    srv.submit(r)
+    with pytest.raises(MemoryError):
+        r.future.result(timeout=10)
+    srv.close()
