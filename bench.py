@@ -65,6 +65,36 @@ def make_inputs(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def committed_traffic(workload, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
+    summary for this workload, or None when there is none or the kernel
+    sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2401_06089_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    for md in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(md) as fh:
+            text = fh.read()
+        m = re.search(r"```json\n(.*?)\n```", text, re.S)
+        if not m:
+            continue
+        try:
+            data = json.loads(m.group(1))
+        except ValueError:
+            continue
+        if data.get("workload") != workload or data.get("source_sha256") != h.hexdigest():
+            continue
+        k = data.get("kernels", {}).get(kernel)
+        if k:
+            return {"bytes_per_launch": k["traffic_bytes_per_dispatch"], "summary": os.path.relpath(md, ROOT),
+                    "rocprof_avg_us": k["avg_us_rocprof"]}
+    return None
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -213,6 +243,13 @@ def main():
                      "algorithmic_GBps": sum(s["bytes"] for s in stages.values()) / (ms_per_step / 1000) / 1e9},
     }
     out["path_hbm"]["frac"] = out["path_hbm"]["algorithmic_GBps"] / HBM_PEAK_GBS
+    tr = committed_traffic(args.workload, dominant)
+    if tr:
+        out["roofline"]["traffic"] = tr["bytes_per_launch"]
+        out["roofline"]["traffic_GBps"] = tr["bytes_per_launch"] / avg_launch_s / 1e9
+        out["roofline"]["traffic_frac"] = out["roofline"]["traffic_GBps"] / HBM_PEAK_GBS
+        out["roofline"]["traffic_source"] = tr["summary"]
+        out["roofline"]["rocprof_avg_launch_ms"] = tr["rocprof_avg_us"] / 1000
     if args.stages:
         out["stages"] = {k: {"ms": s["ms"], "launches": s["launches"],
                              "GBps": (s["bytes"] / (s["ms"] / 1000) / 1e9) if s["ms"] > 0 else None}
