@@ -16,7 +16,7 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;   // 4096 keys per workgroup
 
 enum SortSrc { SRC_WEIGHT = 0, SRC_KEYS = 1 };
-enum SortDst { DST_KEYS = 0, DST_EDGES = 1 };
+enum SortDst { DST_KEYS = 0, DST_RANK = 1 };
 
 struct SortPassArgs {
     int64_t n;
@@ -26,12 +26,8 @@ struct SortPassArgs {
     const uint32_t* keys_in;   // SRC_KEYS
     const int32_t* vals_in;    // SRC_KEYS
     uint32_t* keys_out;        // DST_KEYS
-    int32_t* vals_out;         // DST_KEYS values; DST_EDGES: perm (rank -> edge id)
-    const int32_t* u;          // DST_EDGES: input endpoints (tree-local ids)
-    const int32_t* v;
-    int32_t* ur;               // DST_EDGES: endpoints in rank order (global ids)
-    int32_t* vr;
-    Forest forest;
+    int32_t* vals_out;         // DST_KEYS values; DST_RANK: perm (rank -> edge id)
+    int32_t* rank;             // DST_RANK: rank[edge id] (inverse of perm)
     uint64_t* lb;              // look-back words of this pass, [tiles][kRadix]
     uint64_t* lb_zero;         // look-back words of the next pass, cleared here
     int64_t lb_zero_words;
@@ -44,8 +40,10 @@ struct SortHistArgs {
     int passes;                // digits histogrammed (<= 4)
     const float* w;            // SRC_WEIGHT
     const uint32_t* keys;      // SRC_KEYS
-    int32_t* fill;             // optional: fill[0..fill_n) = kInf
+    uint64_t* fill64;          // optional: fill64[0..fill_n) = all ones
     int64_t fill_n;
+    uint32_t* zero32;          // optional: zero32[0..zero_n) = 0
+    int64_t zero_n;
     uint64_t* lb_zero;         // look-back words of the first pass, cleared here
     int64_t lb_zero_words;
     Control* ctrl;
@@ -63,38 +61,47 @@ constexpr int kScanTile = kScanBlock * kScanItems;   // 2048 edges per workgroup
 
 __host__ __device__ inline int64_t scan_tiles(int64_t m) { return (m + kScanTile - 1) / kScanTile; }
 
+// One edge of a level: endpoints (level-local ids), global rank, and at level 0
+// the global input id (a 16-byte record: one cache-line touch per gather).
+struct alignas(16) EdgeRec {
+    int32_t u, v, r, id;
+};
+
+constexpr uint64_t kNoEdge = ~0ull;          // min64 of a vertex without edges
+constexpr int32_t kLabelFlag = INT32_MIN;    // ptr word holding a final label
+
 struct LevelArgs {
     int32_t m;                 // edges at this level
     int32_t n;                 // vertices at this level
-    const int32_t* eu;         // endpoints (level-local vertex ids)
-    const int32_t* ev;
-    const int32_t* er;         // global rank of each edge (nullptr at level 0)
-    int32_t* minInc;           // lightest incident rank per vertex (flat table + off_j)
-    int32_t* label;            // flat id of the supervertex at j+1 (flat table + off_j)
-    int32_t* minInc_next;      // flat table + off_{j+1}
+    const int32_t* in_u;       // level 0: caller's endpoints (tree-local ids)
+    const int32_t* in_v;
+    const int32_t* rank;       // level 0: rank of each input edge
+    Forest forest;
+    EdgeRec* E;                // this level's edges (level 0: written by k_min_incident)
+    uint64_t* min64;           // per vertex: (rank << 32) | position of its lightest edge
+    int32_t* minInc;           // flat table + off_j: rank of the lightest edge, kInf if none
+    int32_t* label;            // flat table + off_j: flat id of the supervertex at j+1
     int64_t off_next;          // flat offset of level j+1
-    int32_t* ptr;              // contraction pointers (level-local ids)
+    int32_t* ptr;              // contraction pointers / final labels (kLabelFlag set)
+    uint16_t* own;             // per edge: byte 0 = owned by u, byte 1 = owned by v
     uint8_t* alpha;            // per-edge alpha flag
     uint64_t* scan_lb;         // look-back words, one per scan tile
     int32_t* tile_alpha_excl;  // alpha prefix at the start of each scan tile
-    int32_t* out_u;            // next level edges
-    int32_t* out_v;
-    int32_t* out_r;
+    EdgeRec* out;              // next level edges
     int32_t cap_next_e;
     int32_t cap_next_v;
-    int32_t* svflat;           // per rank: flat id of the supervertex an edge is contracted into
-    const int32_t* perm;       // level 0: rank -> global edge id
+    int32_t* svflat;           // per rank: flat id of the supervertex the edge is contracted into
     int32_t* vertex_parent;    // level 0 output (tree-local edge ids)
-    Forest forest;
     Control* ctrl;
     int jump_steps;
     int round;
 };
 
 hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s);
-hipError_t launch_alpha_hook(bool level0, const LevelArgs& a, hipStream_t s);
-hipError_t launch_jump(bool level0, const LevelArgs& a, hipStream_t s);
-hipError_t launch_compact(bool level0, const LevelArgs& a, hipStream_t s);
+hipError_t launch_own(bool level0, const LevelArgs& a, hipStream_t s);
+hipError_t launch_classify(const LevelArgs& a, hipStream_t s);
+hipError_t launch_jump(const LevelArgs& a, hipStream_t s);
+hipError_t launch_compact(const LevelArgs& a, hipStream_t s);
 
 // All remaining levels inside one workgroup's LDS.
 constexpr int kTailThreads = 1024;
@@ -104,9 +111,11 @@ constexpr int kTailV = 8192;
 struct TailArgs {
     int32_t m;
     int32_t n;
-    const int32_t* eu;
-    const int32_t* ev;
-    const int32_t* er;         // nullptr at level 0
+    const EdgeRec* E;          // entry level edges (levels >= 1)
+    const int32_t* in_u;       // level-0 entry: caller's endpoints and ranks
+    const int32_t* in_v;
+    const int32_t* rank;
+    int level0;
     int64_t off;               // flat offset of the entry level
     int64_t flat_cap;
     int32_t* minInc_all;

@@ -1,36 +1,40 @@
 // Recursive tree contraction (paper, Section 3.2) on gfx950.
 //
-// Level j holds m_j edges in ascending rank order (rank = position in the
-// global (weight, id) order; the paper indexes the same order descending) and
-// n_j vertices.  One level does:
+// Ranks: r is an edge's position in the global ascending (weight, id) order,
+// so the paper's descending index is m-1-r and its maxIncident is our
+// lightest incident edge.  Level 0 is processed in the caller's edge order
+// (its vertex accesses then follow whatever locality the input has); deeper
+// levels in compaction order.  Every comparison uses ranks, never positions.
 //
-//   k_min_incident  minInc[x] = lightest incident rank of x.  This is the
-//                   paper's maxIncident (Eq. vertexparent) in ascending ranks;
-//                   at level 0 it is also every vertex's dendrogram parent.
-//   k_alpha_hook    alpha test of Eq. (alphaedge): an edge is alpha iff it is
-//                   the lightest edge of neither endpoint.  Every other edge is
-//                   contracted.  A vertex x points along its lightest edge
-//                   (ptr[x] = other endpoint); ranks strictly fall along
-//                   pointers except across a leaf edge (lightest at both ends),
-//                   whose smaller endpoint becomes the root.  Each supervertex
-//                   therefore is one pointer tree rooted at its unique leaf edge,
-//                   and the supervertices of T_{j+1} are numbered by an
-//                   exclusive scan of leaf flags in rank order (decoupled
-//                   look-back across tiles, alpha count scanned alongside).
-//   k_jump          pointer jumping (in place, bounded steps per launch; the
-//                   host relaunches until every vertex reaches its root), then
-//                   each vertex takes its root's flat label.
-//   k_compact       stable compaction of alpha edges into level j+1 (endpoints
-//                   relabelled, rank kept, so level j+1 is again rank-sorted);
-//                   every contracted edge records the flat id of the
-//                   supervertex it fell into (needed by the expansion).
+// One level, m_j edges and n_j vertices:
+//   k_min_incident  min64[x] = min over incident edges of (rank << 32 | pos):
+//                   the lightest incident edge (Eq. vertexparent) and where
+//                   its record lives.  At level 0 it also builds the 16-byte
+//                   edge records from the caller's arrays, translating the
+//                   tree-local ids of a forest and validating them.
+//   k_own           per vertex: one gather of its lightest edge's record gives
+//                   the hook ptr[x] = other endpoint, the rank table entry and
+//                   (level 0) the vertex's dendrogram parent; the vertex marks
+//                   itself as an owner of that edge.
+//   k_classify      per edge: owned by neither endpoint = alpha (Eq.
+//                   alphaedge); by both = leaf edge.  Ranks fall strictly along
+//                   hooks except across a leaf edge, so every supervertex is one
+//                   pointer tree whose root is its leaf edge's smaller endpoint.
+//                   A decoupled look-back scan of leaf flags (alpha count
+//                   alongside) numbers the next level's vertices; each root's
+//                   ptr word receives its label with the flag bit set.
+//   k_jump          pointer jumping in place (bounded steps per launch; the
+//                   host relaunches until every vertex has its label); each
+//                   vertex writes its flat label and records its lightest
+//                   edge's supervertex for the expansion.
+//   k_compact       stable compaction of alpha edges, endpoints relabelled.
 //
-// Vertices and levels share one flat id space: level j occupies
+// Vertices of all levels share one flat id space: level j occupies
 // [off_j, off_j + n_j).  Isolated vertices (finished components of a forest)
 // are not carried to the next level.
 //
 // k_tail runs every remaining level inside one workgroup's LDS once a level
-// is small, replacing ~4 launches and one host round trip per level.
+// is small, replacing ~5 launches and one host round trip per level.
 #include "kernels.hpp"
 
 namespace pandora {
@@ -44,11 +48,6 @@ constexpr uint64_t kCountMask = ~kFlagMask;
 constexpr uint64_t kLow31 = (1ull << 31) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-__device__ __forceinline__ int32_t local_edge_id(const Forest& f, int32_t gid) {
-    if (f.B == 1) return gid;
-    return (int32_t)(gid - f.edge_base(f.tree_of_edge(gid)));
-}
-
 template <bool L0>
 __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -58,17 +57,61 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
         a.ctrl->not_converged = 0;
     }
     if (i >= a.m) return;
-    const int32_t r = L0 ? (int32_t)i : a.er[i];
-    const int32_t x = a.eu[i];
-    const int32_t y = a.ev[i];
-    // Test first: values only decrease, so a stale read can only cause a
+    EdgeRec e;
+    if (L0) {
+        const int32_t b = a.forest.tree_of_edge(i);
+        const int64_t v0 = a.forest.voff[b];
+        const int64_t nb = a.forest.voff[b + 1] - v0;
+        int64_t x = a.in_u[i];
+        int64_t y = a.in_v[i];
+        if (x < 0 || x >= nb || y < 0 || y >= nb) {
+            raise_err(a.ctrl, kErrBadVertex);
+            x = (x < 0 || x >= nb) ? 0 : x;
+            y = (y < 0 || y >= nb) ? 0 : y;
+        }
+        e.u = (int32_t)(v0 + x);
+        e.v = (int32_t)(v0 + y);
+        e.r = a.rank[i];
+        e.id = (int32_t)i;
+        a.E[i] = e;
+    } else {
+        e = a.E[i];
+    }
+    const uint64_t key = ((uint64_t)(uint32_t)e.r << 32) | (uint64_t)(uint32_t)i;
+    // Read first: values only decrease, so a stale read can only cause a
     // redundant atomic, never a missed one.
-    if (a.minInc[x] > r) atomicMin(&a.minInc[x], r);
-    if (a.minInc[y] > r) atomicMin(&a.minInc[y], r);
+    if (a.min64[e.u] > key) atomicMin((unsigned long long*)&a.min64[e.u], (unsigned long long)key);
+    if (a.min64[e.v] > key) atomicMin((unsigned long long*)&a.min64[e.v], (unsigned long long)key);
 }
 
 template <bool L0>
-__global__ __launch_bounds__(kScanBlock) void k_alpha_hook(LevelArgs a) {
+__global__ __launch_bounds__(256) void k_own(LevelArgs a) {
+    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = x < a.n;
+    const uint64_t mm = live ? a.min64[x] : 0;
+    const bool isolated = live && mm == kNoEdge;
+    const uint64_t b = ballot(isolated);
+    if (b != 0 && lane_id() == __ffsll((long long)b) - 1) atomicAdd(&a.ctrl->isolated, (uint32_t)popc64(b));
+    if (!live) return;
+    if (isolated) {
+        a.minInc[x] = kInf;
+        if (L0) a.vertex_parent[x] = -1;
+        return;
+    }
+    const uint32_t pos = (uint32_t)mm;
+    const EdgeRec e = a.E[pos];
+    const int side = (e.u == (int32_t)x) ? 0 : 1;
+    a.ptr[x] = side ? e.u : e.v;
+    reinterpret_cast<uint8_t*>(a.own)[2 * (int64_t)pos + side] = 1;
+    a.minInc[x] = (int32_t)(mm >> 32);
+    if (L0) {
+        int32_t vp = e.id;
+        if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex(x)));
+        a.vertex_parent[x] = vp;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
     constexpr int W = kScanBlock / kWave;
     __shared__ uint32_t s_ca[kScanItems][W];
     __shared__ uint32_t s_cl[kScanItems][W];
@@ -84,31 +127,20 @@ __global__ __launch_bounds__(kScanBlock) void k_alpha_hook(LevelArgs a) {
     uint32_t lmask = 0;
     uint32_t lpre[kScanItems];
     int32_t root[kScanItems];
+    bool selfloop = false;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t idx = base + k * kScanBlock + tid;
         bool al = false, lf = false;
         root[k] = 0;
         if (idx < a.m) {
-            const int32_t r = L0 ? (int32_t)idx : a.er[idx];
-            const int32_t x = a.eu[idx];
-            const int32_t y = a.ev[idx];
-            const bool ax = a.minInc[x] == r;
-            const bool ay = a.minInc[y] == r;
-            if (ax && ay) {
-                const int32_t lo = x < y ? x : y;
-                const int32_t hi = x < y ? y : x;
-                a.ptr[lo] = lo;
-                a.ptr[hi] = lo;
-                lf = true;
-                root[k] = lo;
-            } else if (ax) {
-                a.ptr[x] = y;
-            } else if (ay) {
-                a.ptr[y] = x;
-            } else {
-                al = true;
-            }
+            const uint16_t o = a.own[idx];
+            a.own[idx] = 0;
+            const EdgeRec e = a.E[idx];
+            selfloop |= e.u == e.v;
+            al = o == 0;
+            lf = o == 0x0101;
+            root[k] = e.u < e.v ? e.u : e.v;
             a.alpha[idx] = al ? 1 : 0;
         }
         const uint64_t ba = ballot(al);
@@ -120,6 +152,7 @@ __global__ __launch_bounds__(kScanBlock) void k_alpha_hook(LevelArgs a) {
             s_cl[k][wave] = (uint32_t)popc64(bl);
         }
     }
+    if (ballot(selfloop) != 0 && lane == 0) raise_err(a.ctrl, kErrNotTree);
     __syncthreads();
     if (tid == 0) {
         uint32_t sa = 0, sl = 0;
@@ -170,51 +203,47 @@ __global__ __launch_bounds__(kScanBlock) void k_alpha_hook(LevelArgs a) {
     for (int k = 0; k < kScanItems; ++k) {
         if (lmask & (1u << k)) {
             const int64_t pos = leaf_base + s_cl[k][wave] + lpre[k];
-            a.label[root[k]] = (int32_t)(a.off_next + pos);
+            a.ptr[root[k]] = kLabelFlag | (int32_t)pos;
         }
     }
 }
 
-template <bool L0>
 __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
     const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (x >= a.n) return;
-    const int32_t mi = a.minInc[x];
-    const bool isolated = mi == kInf;
     if (a.round == 0) {
-        if (L0) {
-            int32_t vp = -1;
-            if (!isolated) {
-                vp = a.perm[mi];
-                if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex(x)));
-            }
-            a.vertex_parent[x] = vp;
-        }
         int32_t nn = a.ctrl->n_next;
         if (nn > a.cap_next_v) nn = a.cap_next_v;
-        if (x < nn) a.minInc_next[x] = kInf;
-        const uint64_t b = ballot(isolated);
-        if (b != 0 && (threadIdx.x & (kWave - 1)) == (uint32_t)__ffsll((long long)b) - 1)
-            atomicAdd(&a.ctrl->isolated, (uint32_t)popc64(b));
-        if (isolated) a.label[x] = -1;
+        if (x < nn) a.min64[x] = kNoEdge;     // the next level starts clean
     }
-    if (isolated) return;
-    int32_t p = a.ptr[x];
-    if (p == x) return;                       // root: labelled by k_alpha_hook
-    int32_t pp = a.ptr[p];
-    for (int s = 0; pp != p && s < a.jump_steps; ++s) {
-        p = pp;
-        pp = a.ptr[p];
-    }
-    a.ptr[x] = p;
-    if (pp != p) {
-        atomicOr(&a.ctrl->not_converged, 1u << (a.round & 31));
+    const int32_t r = a.minInc[x];
+    if (r == kInf) {
+        if (a.round == 0) a.label[x] = -1;
         return;
     }
-    a.label[x] = a.label[p];
+    int32_t q = a.ptr[x];
+    int32_t lab;
+    if (q & kLabelFlag) {
+        lab = q & ~kLabelFlag;
+    } else {
+        int32_t t = a.ptr[q];
+        for (int s = 0; !(t & kLabelFlag) && s < a.jump_steps; ++s) {
+            q = t;
+            t = a.ptr[q];
+        }
+        if (!(t & kLabelFlag)) {
+            a.ptr[x] = q;                        // progress for the next launch
+            atomicOr(&a.ctrl->not_converged, 1u << (a.round & 31));
+            return;
+        }
+        lab = t & ~kLabelFlag;
+        a.ptr[x] = t;                            // x now holds its label directly
+    }
+    const int32_t flat = (int32_t)(a.off_next + lab);
+    a.label[x] = flat;
+    a.svflat[r] = flat;                          // the lightest edge of x falls into this supervertex
 }
 
-template <bool L0>
 __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
     constexpr int W = kScanBlock / kWave;
     __shared__ uint32_t s_ca[kScanItems][W];
@@ -248,23 +277,22 @@ __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
     bool selfloop = false, overflow = false;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
+        if (!(amask & (1u << k))) continue;
         const int64_t idx = base + k * kScanBlock + tid;
-        if (idx >= a.m) continue;
-        const int32_t r = L0 ? (int32_t)idx : a.er[idx];
-        const int32_t lx = a.label[a.eu[idx]];
-        if (amask & (1u << k)) {
-            const int32_t ly = a.label[a.ev[idx]];
-            const int64_t pos = abase + s_ca[k][wave] + apre[k];
-            selfloop |= lx == ly;
-            if (pos < a.cap_next_e) {
-                a.out_u[pos] = (int32_t)(lx - a.off_next);
-                a.out_v[pos] = (int32_t)(ly - a.off_next);
-                a.out_r[pos] = r;
-            } else {
-                overflow = true;
-            }
+        const EdgeRec e = a.E[idx];
+        const int32_t lx = a.label[e.u];
+        const int32_t ly = a.label[e.v];
+        const int64_t pos = abase + s_ca[k][wave] + apre[k];
+        selfloop |= lx == ly;
+        if (pos < a.cap_next_e) {
+            EdgeRec o;
+            o.u = (int32_t)(lx - a.off_next);
+            o.v = (int32_t)(ly - a.off_next);
+            o.r = e.r;
+            o.id = 0;
+            a.out[pos] = o;
         } else {
-            a.svflat[r] = lx;
+            overflow = true;
         }
     }
     if (ballot(selfloop) != 0 && lane == 0) raise_err(a.ctrl, kErrNotTree);
@@ -300,7 +328,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     __shared__ uint32_t s_wsum[kTailThreads / kWave];
     __shared__ uint32_t s_flag;
     const int tid = threadIdx.x;
-    const bool level0 = a.er == nullptr;
+    const bool level0 = a.level0 != 0;
 
     int32_t m = a.m, n = a.n;
     int64_t off = a.off;
@@ -308,9 +336,25 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     int levels = 0;
     uint32_t err = 0;
     for (int i = tid; i < m; i += kTailThreads) {
-        s_u[i] = a.eu[i];
-        s_v[i] = a.ev[i];
-        s_r[i] = level0 ? i : a.er[i];
+        if (level0) {
+            const int32_t b = a.forest.tree_of_edge(i);
+            const int64_t v0 = a.forest.voff[b];
+            const int64_t nb = a.forest.voff[b + 1] - v0;
+            int64_t x = a.in_u[i], y = a.in_v[i];
+            if (x < 0 || x >= nb || y < 0 || y >= nb) {
+                err |= kErrBadVertex;
+                x = (x < 0 || x >= nb) ? 0 : x;
+                y = (y < 0 || y >= nb) ? 0 : y;
+            }
+            s_u[i] = (int32_t)(v0 + x);
+            s_v[i] = (int32_t)(v0 + y);
+            s_r[i] = a.rank[i];
+        } else {
+            const EdgeRec e = a.E[i];
+            s_u[i] = e.u;
+            s_v[i] = e.v;
+            s_r[i] = e.r;
+        }
     }
     __syncthreads();
 
@@ -331,6 +375,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
             const int i = tid * kTailPer + q;
             if (i >= m) break;
             const int32_t r = s_r[i], x = s_u[i], y = s_v[i];
+            if (x == y) err |= kErrNotTree;
             const bool ax = s_min[x] == r, ay = s_min[y] == r;
             if (ax && ay) {
                 const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
@@ -440,7 +485,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         }
     }
     // last level: no edges left, every vertex is its component's root chain
-    if (!err && off + n <= a.flat_cap) {
+    if (!(err & kErrOverflow) && off + n <= a.flat_cap) {
         for (int x = tid; x < n; x += kTailThreads) {
             a.minInc_all[off + x] = kInf;
             a.label_all[off + x] = -1;
@@ -469,23 +514,24 @@ hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_alpha_hook(bool level0, const LevelArgs& a, hipStream_t s) {
-    const unsigned g = (unsigned)scan_tiles(a.m);
-    if (level0) k_alpha_hook<true><<<g, kScanBlock, 0, s>>>(a);
-    else k_alpha_hook<false><<<g, kScanBlock, 0, s>>>(a);
+hipError_t launch_own(bool level0, const LevelArgs& a, hipStream_t s) {
+    if (level0) k_own<true><<<blocks_for(a.n, 256), 256, 0, s>>>(a);
+    else k_own<false><<<blocks_for(a.n, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_jump(bool level0, const LevelArgs& a, hipStream_t s) {
-    if (level0) k_jump<true><<<blocks_for(a.n, 256), 256, 0, s>>>(a);
-    else k_jump<false><<<blocks_for(a.n, 256), 256, 0, s>>>(a);
+hipError_t launch_classify(const LevelArgs& a, hipStream_t s) {
+    k_classify<<<(unsigned)scan_tiles(a.m), kScanBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_compact(bool level0, const LevelArgs& a, hipStream_t s) {
-    const unsigned g = (unsigned)scan_tiles(a.m);
-    if (level0) k_compact<true><<<g, kScanBlock, 0, s>>>(a);
-    else k_compact<false><<<g, kScanBlock, 0, s>>>(a);
+hipError_t launch_jump(const LevelArgs& a, hipStream_t s) {
+    k_jump<<<blocks_for(a.n, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const LevelArgs& a, hipStream_t s) {
+    k_compact<<<(unsigned)scan_tiles(a.m), kScanBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 

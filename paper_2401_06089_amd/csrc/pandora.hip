@@ -41,8 +41,8 @@ struct Layout {
     std::vector<int64_t> capE, capV;
     int64_t flat_cap = 0;
     int chain_passes = 0;
-    size_t ctrl, voff, K0, K1, V0, V1, perm, ur, vr, EA[3], EB[3], alpha, scan_lb, tile_excl,
-        minInc, label, ptr, svflat, lb0, lb1;
+    size_t ctrl, voff, K0, K1, V0, V1, perm, rank, E0, EA, EB, min64, own, alpha, scan_lb,
+        tile_excl, minInc, label, ptr, svflat, lb0, lb1;
     size_t total = 0;
 };
 
@@ -93,10 +93,12 @@ Layout make_layout(int64_t N, int32_t B) {
     L.V0 = take(c, 4 * M);
     L.V1 = take(c, 4 * M);
     L.perm = take(c, 4 * M);
-    L.ur = take(c, 4 * M);
-    L.vr = take(c, 4 * M);
-    for (int k = 0; k < 3; ++k) L.EA[k] = take(c, 4 * E1);
-    for (int k = 0; k < 3; ++k) L.EB[k] = take(c, 4 * E2);
+    L.rank = take(c, 4 * M);
+    L.E0 = take(c, sizeof(EdgeRec) * M);
+    L.EA = take(c, sizeof(EdgeRec) * E1);
+    L.EB = take(c, sizeof(EdgeRec) * E2);
+    L.min64 = take(c, 8 * N);
+    L.own = take(c, 2 * M);
     L.alpha = take(c, M);
     L.scan_lb = take(c, 8 * scant);
     L.tile_excl = take(c, 4 * scant);
@@ -134,15 +136,15 @@ thread_local Stats g_last;
 // (different templates, different sizes per launch).
 enum ProfKind {
     PK_ZERO, PK_SORT_HIST, PK_SORT_W_FIRST, PK_SORT_W_MID, PK_SORT_W_LAST, PK_MIN_INC,
-    PK_ALPHA_HOOK, PK_JUMP, PK_COMPACT, PK_TAIL, PK_WALK_HIST, PK_SORT_C_PASS, PK_STITCH,
-    PK_MIN_INC_N, PK_ALPHA_HOOK_N, PK_JUMP_N, PK_COMPACT_N,
+    PK_OWN, PK_CLASSIFY, PK_JUMP, PK_COMPACT, PK_TAIL, PK_WALK_HIST, PK_SORT_C_PASS, PK_STITCH,
+    PK_MIN_INC_N, PK_OWN_N, PK_CLASSIFY_N, PK_JUMP_N, PK_COMPACT_N,
     PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "zero_control", "sort_hist", "sort_pass_weight_first", "sort_pass_weight_mid",
-    "sort_pass_weight_last", "min_incident_l0", "alpha_hook_l0", "jump_l0", "compact_l0", "tail",
-    "walk_hist", "sort_pass_chain", "stitch", "min_incident_ln", "alpha_hook_ln", "jump_ln",
-    "compact_ln"};
+    "sort_pass_weight_last", "min_incident_l0", "own_l0", "classify_l0", "jump_l0", "compact_l0",
+    "tail", "walk_hist", "sort_pass_chain", "stitch", "min_incident_ln", "own_ln", "classify_ln",
+    "jump_ln", "compact_ln"};
 
 struct Prof {
     std::mutex mu;
@@ -310,8 +312,6 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     int32_t* V[2] = {at<int32_t>(d, L.V0), at<int32_t>(d, L.V1)};
     uint64_t* LB[2] = {at<uint64_t>(d, L.lb0), at<uint64_t>(d, L.lb1)};
     int32_t* perm = at<int32_t>(d, L.perm);
-    int32_t* ur = at<int32_t>(d, L.ur);
-    int32_t* vr = at<int32_t>(d, L.vr);
     int32_t* minInc_all = at<int32_t>(d, L.minInc);
     int32_t* label_all = at<int32_t>(d, L.label);
     int32_t* svflat = at<int32_t>(d, L.svflat);
@@ -320,18 +320,23 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     PD_TIMED(PK_ZERO, sizeof(Control), launch_zero_control(ctrl, s));
 
     // ---- 1. weight sort --------------------------------------------------------
+    uint64_t* min64 = at<uint64_t>(d, L.min64);
+    uint16_t* own = at<uint16_t>(d, L.own);
+    int32_t* rank = at<int32_t>(d, L.rank);
     {
         SortHistArgs h{};
         h.n = M;
         h.hist_row = 0;
         h.passes = 4;
         h.w = w;
-        h.fill = minInc_all;        // level-0 minInc starts at +inf
+        h.fill64 = min64;           // level 0 starts with no lightest edge
         h.fill_n = N;
+        h.zero32 = reinterpret_cast<uint32_t*>(own);
+        h.zero_n = (2 * M + 3) / 4;
         h.lb_zero = LB[0];
         h.lb_zero_words = lb_words;
         h.ctrl = ctrl;
-        PD_TIMED(PK_SORT_HIST, 4.0 * M + 4.0 * N, launch_sort_hist(SRC_WEIGHT, h, s));
+        PD_TIMED(PK_SORT_HIST, 4.0 * M + 8.0 * N + 2.0 * M, launch_sort_hist(SRC_WEIGHT, h, s));
         const uint32_t* kin = nullptr;
         const int32_t* vin = nullptr;
         for (int p = 0; p < 4; ++p) {
@@ -344,66 +349,63 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
             a.vals_in = vin;
             a.keys_out = K[p & 1];
             a.vals_out = (p == 3) ? perm : V[p & 1];
-            a.u = u;
-            a.v = v;
-            a.ur = ur;
-            a.vr = vr;
-            a.forest = forest;
+            a.rank = rank;
             a.lb = LB[p & 1];
             a.lb_zero = LB[(p + 1) & 1];
             a.lb_zero_words = lb_words;
             a.ctrl = ctrl;
             const int kind = p == 0 ? PK_SORT_W_FIRST : (p == 3 ? PK_SORT_W_LAST : PK_SORT_W_MID);
-            const double by = (p == 0 ? 12.0 : (p == 3 ? 28.0 : 16.0)) * M;
-            PD_TIMED(kind, by, launch_sort_pass(p == 0 ? SRC_WEIGHT : SRC_KEYS, p == 3 ? DST_EDGES : DST_KEYS, a, s));
+            const double by = (p == 0 ? 12.0 : 16.0) * M;
+            PD_TIMED(kind, by, launch_sort_pass(p == 0 ? SRC_WEIGHT : SRC_KEYS, p == 3 ? DST_RANK : DST_KEYS, a, s));
             kin = K[p & 1];
             vin = V[p & 1];
         }
     }
 
     // ---- 2. contraction levels --------------------------------------------------
-    int32_t* EA[3] = {at<int32_t>(d, L.EA[0]), at<int32_t>(d, L.EA[1]), at<int32_t>(d, L.EA[2])};
-    int32_t* EB[3] = {at<int32_t>(d, L.EB[0]), at<int32_t>(d, L.EB[1]), at<int32_t>(d, L.EB[2])};
-    const int32_t* eu = ur;
-    const int32_t* ev = vr;
-    const int32_t* er = nullptr;
+    EdgeRec* E0 = at<EdgeRec>(d, L.E0);
+    EdgeRec* EA = at<EdgeRec>(d, L.EA);
+    EdgeRec* EB = at<EdgeRec>(d, L.EB);
+    EdgeRec* E = E0;
     int64_t m = M, n = N, off = 0;
     int j = 0;
     while (m > 0 && (m > kTailE || n > kTailV)) {
         if (j >= L.Lmax) return PANDORA_ERR_NOT_A_TREE;
         const bool l0 = j == 0;
-        int32_t** out = (j % 2 == 0) ? EA : EB;
+        EdgeRec* out = (j % 2 == 0) ? EA : EB;
         LevelArgs a{};
         a.m = (int32_t)m;
         a.n = (int32_t)n;
-        a.eu = eu;
-        a.ev = ev;
-        a.er = er;
+        a.in_u = u;
+        a.in_v = v;
+        a.rank = rank;
+        a.forest = forest;
+        a.E = E;
+        a.min64 = min64;
         a.minInc = minInc_all + off;
         a.label = label_all + off;
-        a.minInc_next = minInc_all + off + n;
         a.off_next = off + n;
         a.ptr = at<int32_t>(d, L.ptr);
+        a.own = own;
         a.alpha = at<uint8_t>(d, L.alpha);
         a.scan_lb = at<uint64_t>(d, L.scan_lb);
         a.tile_alpha_excl = at<int32_t>(d, L.tile_excl);
-        a.out_u = out[0];
-        a.out_v = out[1];
-        a.out_r = out[2];
+        a.out = out;
         a.cap_next_e = (int32_t)L.capE[j + 1];
         a.cap_next_v = (int32_t)L.capV[j + 1];
         a.svflat = svflat;
-        a.perm = perm;
         a.vertex_parent = vertex_parent;
-        a.forest = forest;
         a.ctrl = ctrl;
         a.jump_steps = kJumpSteps;
-        PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 16.0 : 20.0) * m + 4.0 * n, launch_min_incident(l0, a, s));
-        PD_TIMED(l0 ? PK_ALPHA_HOOK : PK_ALPHA_HOOK_N, (l0 ? 17.0 : 21.0) * m + 4.0 * n, launch_alpha_hook(l0, a, s));
+        PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 28.0 : 12.0) * m + 8.0 * n,
+                 launch_min_incident(l0, a, s));
+        PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 28.0 : 24.0) * n, launch_own(l0, a, s));
+        PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 21.0 * m,
+                 launch_classify(a, s));
         for (int round = 0;; ++round) {
             if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
             a.round = round;
-            PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? (l0 ? 32.0 : 24.0) : 20.0) * n, launch_jump(l0, a, s));
+            PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 24.0 : 16.0) * n, launch_jump(a, s));
             ++st.jump_launches;
             rc = read_ctrl(ws, ctrl, hctrl, s);
             if (rc != PANDORA_OK) return rc;
@@ -413,15 +415,13 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
         if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
             return PANDORA_ERR_NOT_A_TREE;
-        PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, (l0 ? 13.0 : 17.0) * m + 16.0 * m_next, launch_compact(l0, a, s));
+        PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 40.0 * m_next, launch_compact(a, s));
         st.sum_edges += m;
         ++st.levels;
         off += n;
         n = n_next;
         m = m_next;
-        eu = out[0];
-        ev = out[1];
-        er = out[2];
+        E = out;
         ++j;
     }
 
@@ -430,9 +430,11 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         TailArgs t{};
         t.m = (int32_t)m;
         t.n = (int32_t)n;
-        t.eu = eu;
-        t.ev = ev;
-        t.er = er;
+        t.E = E;
+        t.in_u = u;
+        t.in_v = v;
+        t.rank = rank;
+        t.level0 = j == 0 ? 1 : 0;
         t.off = off;
         t.flat_cap = L.flat_cap;
         t.minInc_all = minInc_all;
@@ -444,7 +446,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         t.ctrl = ctrl;
         st.tail_entry_edges = m;
         st.sum_edges += m;
-        PD_TIMED(PK_TAIL, 12.0 * m, launch_tail(t, s));
+        PD_TIMED(PK_TAIL, 16.0 * m, launch_tail(t, s));
     }
 
     // ---- 4. expansion -----------------------------------------------------------------
@@ -474,7 +476,6 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
             a.vals_in = vin;
             a.keys_out = K[(p + 1) & 1];
             a.vals_out = V[(p + 1) & 1];
-            a.forest = forest;
             a.lb = LB[p & 1];
             a.lb_zero = LB[(p + 1) & 1];
             a.lb_zero_words = lb_words;

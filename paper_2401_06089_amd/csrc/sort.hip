@@ -15,9 +15,8 @@
 //
 // Keys of the first sort are the monotone u32 image of the fp32 weights
 // (the value carried is the edge id, generated rather than read); the last
-// pass of that sort writes the rank->edge permutation and gathers the two
-// endpoints of each edge into rank order, translating tree-local ids of a
-// batched forest into global ids and validating them on the way.
+// pass of that sort writes the rank -> edge permutation and scatters its
+// inverse, the rank of every edge, so that level 0 can run in input order.
 #include "kernels.hpp"
 
 namespace pandora {
@@ -68,7 +67,8 @@ __global__ __launch_bounds__(256) void k_sort_hist(SortHistArgs a) {
         for (int p = 0; p < a.passes; ++p)
             atomicAdd(&s_h[p][(key >> (kSortBits * p)) & (kRadix - 1)], 1u);
     }
-    for (int64_t i = t0; i < a.fill_n; i += stride) a.fill[i] = kInf;
+    for (int64_t i = t0; i < a.fill_n; i += stride) a.fill64[i] = ~0ull;
+    for (int64_t i = t0; i < a.zero_n; i += stride) a.zero32[i] = 0;
     for (int64_t i = t0; i < a.lb_zero_words; i += stride) a.lb_zero[i] = 0;
     if (SRC == SRC_WEIGHT && ballot(nan_seen) != 0 && lane_id() == 0) raise_err(a.ctrl, kErrNaN);
     __syncthreads();
@@ -205,37 +205,28 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
     // Scatter: consecutive threads take consecutive LDS slots, so each digit's
     // run lands on consecutive global slots.
     const int tile_n = (int)((a.n - base) < kSortTile ? (a.n - base) : kSortTile);
-    bool bad = false;
     for (int i = tid; i < tile_n; i += kSortBlock) {
         const uint32_t kk = s_keys[i];
         const int64_t g = s_gbase[(kk >> a.shift) & (kRadix - 1)] + i;
         const int32_t id = s_vals[i];
         // Only reachable after a look-back failure (already reported): never
-        // write or gather outside the arrays.
-        if (g < 0 || g >= a.n || (DST == DST_EDGES && (id < 0 || id >= a.n))) continue;
+        // write outside the arrays.
+        if (g < 0 || g >= a.n || (DST == DST_RANK && (id < 0 || id >= a.n))) continue;
         if (DST == DST_KEYS) {
             a.keys_out[g] = kk;
             a.vals_out[g] = id;
         } else {
             a.vals_out[g] = id;
-            const int32_t b = a.forest.tree_of_edge(id);
-            const int64_t v0 = a.forest.voff[b];
-            const int64_t nb = a.forest.voff[b + 1] - v0;
-            int64_t x = a.u[id];
-            int64_t y = a.v[id];
-            if (x < 0 || x >= nb) { bad = true; x = 0; }
-            if (y < 0 || y >= nb) { bad = true; y = 0; }
-            a.ur[g] = (int32_t)(v0 + x);
-            a.vr[g] = (int32_t)(v0 + y);
+            a.rank[id] = (int32_t)g;
         }
     }
-    if (DST == DST_EDGES && ballot(bad) != 0 && lane == 0) raise_err(a.ctrl, kErrBadVertex);
 }
 
 }  // namespace
 
 hipError_t launch_sort_hist(int src, const SortHistArgs& a, hipStream_t s) {
-    const int64_t work = a.n > a.fill_n ? a.n : a.fill_n;
+    int64_t work = a.n > a.fill_n ? a.n : a.fill_n;
+    if (a.zero_n > work) work = a.zero_n;
     int64_t blocks = (work + 256 * 16 - 1) / (256 * 16);
     if (blocks < 1) blocks = 1;
     if (blocks > 4096) blocks = 4096;
@@ -251,9 +242,9 @@ hipError_t launch_sort_pass(int src, int dst, const SortPassArgs& a, hipStream_t
     if (tiles < 1) return hipSuccess;
     const dim3 grid((unsigned)tiles), block(kSortBlock);
     if (src == SRC_WEIGHT && dst == DST_KEYS) k_sort_pass<SRC_WEIGHT, DST_KEYS><<<grid, block, 0, s>>>(a);
-    else if (src == SRC_WEIGHT) k_sort_pass<SRC_WEIGHT, DST_EDGES><<<grid, block, 0, s>>>(a);
+    else if (src == SRC_WEIGHT) k_sort_pass<SRC_WEIGHT, DST_RANK><<<grid, block, 0, s>>>(a);
     else if (dst == DST_KEYS) k_sort_pass<SRC_KEYS, DST_KEYS><<<grid, block, 0, s>>>(a);
-    else k_sort_pass<SRC_KEYS, DST_EDGES><<<grid, block, 0, s>>>(a);
+    else k_sort_pass<SRC_KEYS, DST_RANK><<<grid, block, 0, s>>>(a);
     return hipGetLastError();
 }
 
