@@ -232,6 +232,7 @@ def main():
                    "edges_per_step": total_edges, "vertices_per_step": total_vertices,
                    "calls_per_step": len(calls), "parallelism": "single GPU"},
         "mpoints_per_s": total_vertices * args.steps / elapsed / 1e6,
+        "last_call_stats": pd.last_stats(),
         "latency_ms": {"p50": 1000 * statistics.median(lat),
                        "p99": 1000 * float(np.percentile(lat, 99)),
                        "per": "step"},

@@ -29,7 +29,7 @@ struct Control {
     int32_t tail_levels;      // levels finished inside the LDS tail kernel
     int32_t tail_vertices;    // vertices of the last level (all isolated)
     uint32_t sort_tiles[8];   // dynamic tile counters, one per radix pass
-    uint32_t hist[8][256];    // per-pass digit histograms (8-bit digits)
+    uint32_t hist[8][512];    // per-pass digit histograms (8- or 9-bit digits)
 };
 
 // A forest of B trees: tree b owns vertices [voff[b], voff[b+1]) and edges

@@ -8,7 +8,7 @@
 // with no incident edge (the last level, or a finished component of a forest)
 // has p = +inf and ends the walk: that is the component's root chain.  With
 // the flat vertex numbering the walk is a pointer chase
-//   x <- svflat[r];  while (r >= minInc_all[x]) x <- label_all[x];
+//   x <- svflat[r];  while (r >= vinfo[x].minInc) x <- vinfo[x].label;
 // and the final x identifies the chain (k_walk_hist, which also histograms
 // the chain keys for the sort that follows).
 //
@@ -25,8 +25,10 @@ namespace {
 constexpr int kWalkLimit = 64;
 
 __global__ __launch_bounds__(256) void k_walk_hist(WalkArgs a) {
-    __shared__ uint32_t s_h[4][kRadix];
-    for (int i = threadIdx.x; i < 4 * kRadix; i += blockDim.x) (&s_h[0][0])[i] = 0;
+    __shared__ uint32_t s_h[4][kMaxRadix];
+    const int radix = 1 << a.bits;
+    const uint32_t mask = (uint32_t)radix - 1u;
+    for (int i = threadIdx.x; i < 4 * kMaxRadix; i += blockDim.x) (&s_h[0][0])[i] = 0;
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -39,20 +41,20 @@ __global__ __launch_bounds__(256) void k_walk_hist(WalkArgs a) {
                 x = a.n0;
                 break;
             }
-            if (r < (int64_t)a.minInc_all[x]) break;
-            x = a.label_all[x];
+            const VInfo vi = a.vinfo_all[x];
+            if (r < (int64_t)vi.minInc) break;
+            x = vi.label;
         }
         const uint32_t key = (uint32_t)(x - a.n0);
         a.ckey[r] = key;
-        for (int p = 0; p < a.passes; ++p)
-            atomicAdd(&s_h[p][(key >> (kSortBits * p)) & (kRadix - 1)], 1u);
+        for (int p = 0; p < a.passes; ++p) atomicAdd(&s_h[p][(key >> (a.bits * p)) & mask], 1u);
     }
     for (int64_t i = t0; i < a.lb_zero_words; i += stride) a.lb_zero[i] = 0;
     if (ballot(bad) != 0 && lane_id() == 0) raise_err(a.ctrl, kErrWalk);
     __syncthreads();
-    for (int i = threadIdx.x; i < a.passes * kRadix; i += blockDim.x) {
-        const uint32_t c = (&s_h[0][0])[i];
-        if (c) atomicAdd(&a.ctrl->hist[a.hist_row + i / kRadix][i % kRadix], c);
+    for (int i = threadIdx.x; i < a.passes * radix; i += blockDim.x) {
+        const uint32_t c = s_h[i / radix][i % radix];
+        if (c) atomicAdd(&a.ctrl->hist[a.hist_row + i / radix][i % radix], c);
     }
 }
 
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
     if (i + 1 < a.m && a.skey[i + 1] == c) {
         parent = a.sid[i + 1];
     } else {
-        const int32_t p = a.minInc_all[a.n0 + (int64_t)c];
+        const int32_t p = a.vinfo_all[a.n0 + (int64_t)c].minInc;
         parent = (p < 0 || p >= a.m) ? -1 : a.perm[p];
     }
     if (parent >= 0 && a.forest.B > 1)

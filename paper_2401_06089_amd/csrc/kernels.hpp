@@ -9,17 +9,24 @@
 namespace pandora {
 
 // ---- radix sort (stable LSD, 8-bit digits, one-sweep chained scan) ----------
-constexpr int kSortBits = 8;
-constexpr int kRadix = 1 << kSortBits;
-constexpr int kSortBlock = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortBlock * kSortItems;   // 4096 keys per workgroup
+#ifndef PANDORA_SORT_BLOCK
+#define PANDORA_SORT_BLOCK 512
+#endif
+#ifndef PANDORA_SORT_ITEMS
+#define PANDORA_SORT_ITEMS 16
+#endif
+constexpr int kMaxRadixBits = 9;                      // digits of 8 or 9 bits
+constexpr int kMaxRadix = 1 << kMaxRadixBits;
+constexpr int kSortBlock = PANDORA_SORT_BLOCK;
+constexpr int kSortItems = PANDORA_SORT_ITEMS;
+constexpr int kSortTile = kSortBlock * kSortItems;   // keys per workgroup
 
 enum SortSrc { SRC_WEIGHT = 0, SRC_KEYS = 1 };
 enum SortDst { DST_KEYS = 0, DST_RANK = 1 };
 
 struct SortPassArgs {
     int64_t n;
+    int bits;                  // digit width of this pass: 8 or 9
     int shift;                 // bit offset of this pass's digit
     int pass;                  // row of Control::hist / sort_tiles
     const float* w;            // SRC_WEIGHT: keys from weights, values = index
@@ -28,7 +35,7 @@ struct SortPassArgs {
     uint32_t* keys_out;        // DST_KEYS
     int32_t* vals_out;         // DST_KEYS values; DST_RANK: perm (rank -> edge id)
     int32_t* rank;             // DST_RANK: rank[edge id] (inverse of perm)
-    uint64_t* lb;              // look-back words of this pass, [tiles][kRadix]
+    uint64_t* lb;              // look-back words of this pass, [tiles][1 << bits]
     uint64_t* lb_zero;         // look-back words of the next pass, cleared here
     int64_t lb_zero_words;
     Control* ctrl;
@@ -36,6 +43,7 @@ struct SortPassArgs {
 
 struct SortHistArgs {
     int64_t n;
+    int bits;                  // digit width: 8 or 9
     int hist_row;              // first Control::hist row written
     int passes;                // digits histogrammed (<= 4)
     const float* w;            // SRC_WEIGHT
@@ -67,6 +75,13 @@ struct alignas(16) EdgeRec {
     int32_t u, v, r, id;
 };
 
+// Per flat vertex: rank of its lightest edge at its level (kInf if none) and
+// the flat id of its supervertex one level up (-1 if none); one 8-byte record,
+// so a step of the expansion walk touches one cache line.
+struct alignas(8) VInfo {
+    int32_t minInc, label;
+};
+
 constexpr uint64_t kNoEdge = ~0ull;          // min64 of a vertex without edges
 constexpr int32_t kLabelFlag = INT32_MIN;    // ptr word holding a final label
 
@@ -79,8 +94,7 @@ struct LevelArgs {
     Forest forest;
     EdgeRec* E;                // this level's edges (level 0: written by k_min_incident)
     uint64_t* min64;           // per vertex: (rank << 32) | position of its lightest edge
-    int32_t* minInc;           // flat table + off_j: rank of the lightest edge, kInf if none
-    int32_t* label;            // flat table + off_j: flat id of the supervertex at j+1
+    VInfo* vinfo;              // flat table + off_j
     int64_t off_next;          // flat offset of level j+1
     int32_t* ptr;              // contraction pointers / final labels (kLabelFlag set)
     uint16_t* own;             // per edge: byte 0 = owned by u, byte 1 = owned by v
@@ -118,8 +132,7 @@ struct TailArgs {
     int level0;
     int64_t off;               // flat offset of the entry level
     int64_t flat_cap;
-    int32_t* minInc_all;
-    int32_t* label_all;
+    VInfo* vinfo_all;
     int32_t* svflat;
     const int32_t* perm;
     int32_t* vertex_parent;
@@ -135,9 +148,9 @@ struct WalkArgs {
     int64_t n0;                // vertices of level 0 = flat offset of level 1
     int64_t flat_cap;
     const int32_t* svflat;
-    const int32_t* minInc_all;
-    const int32_t* label_all;
+    const VInfo* vinfo_all;
     uint32_t* ckey;            // out: chain key per rank
+    int bits;                  // digit width of the chain sort
     int hist_row;
     int passes;
     uint64_t* lb_zero;
@@ -151,7 +164,7 @@ struct StitchArgs {
     int64_t flat_cap;
     const uint32_t* skey;      // chain keys sorted
     const int32_t* sid;        // edge ids in chain order
-    const int32_t* minInc_all;
+    const VInfo* vinfo_all;
     const int32_t* perm;
     int32_t* edge_parent;
     Forest forest;

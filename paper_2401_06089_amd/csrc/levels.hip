@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_own(LevelArgs a) {
     if (b != 0 && lane_id() == __ffsll((long long)b) - 1) atomicAdd(&a.ctrl->isolated, (uint32_t)popc64(b));
     if (!live) return;
     if (isolated) {
-        a.minInc[x] = kInf;
+        a.vinfo[x].minInc = kInf;
         if (L0) a.vertex_parent[x] = -1;
         return;
     }
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_own(LevelArgs a) {
     const int side = (e.u == (int32_t)x) ? 0 : 1;
     a.ptr[x] = side ? e.u : e.v;
     reinterpret_cast<uint8_t*>(a.own)[2 * (int64_t)pos + side] = 1;
-    a.minInc[x] = (int32_t)(mm >> 32);
+    a.vinfo[x].minInc = (int32_t)(mm >> 32);
     if (L0) {
         int32_t vp = e.id;
         if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex(x)));
@@ -216,9 +216,9 @@ __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
         if (nn > a.cap_next_v) nn = a.cap_next_v;
         if (x < nn) a.min64[x] = kNoEdge;     // the next level starts clean
     }
-    const int32_t r = a.minInc[x];
+    const int32_t r = a.vinfo[x].minInc;
     if (r == kInf) {
-        if (a.round == 0) a.label[x] = -1;
+        if (a.round == 0) a.vinfo[x].label = -1;
         return;
     }
     int32_t q = a.ptr[x];
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
         a.ptr[x] = t;                            // x now holds its label directly
     }
     const int32_t flat = (int32_t)(a.off_next + lab);
-    a.label[x] = flat;
+    a.vinfo[x].label = flat;
     a.svflat[r] = flat;                          // the lightest edge of x falls into this supervertex
 }
 
@@ -280,8 +280,8 @@ __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
         if (!(amask & (1u << k))) continue;
         const int64_t idx = base + k * kScanBlock + tid;
         const EdgeRec e = a.E[idx];
-        const int32_t lx = a.label[e.u];
-        const int32_t ly = a.label[e.v];
+        const int32_t lx = a.vinfo[e.u].label;
+        const int32_t ly = a.vinfo[e.v].label;
         const int64_t pos = abase + s_ca[k][wave] + apre[k];
         selfloop |= lx == ly;
         if (pos < a.cap_next_e) {
@@ -432,8 +432,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
             int32_t lab = -1;
             if (mi == kInf) ++iso;
             else lab = s_lab[s_ptr[x]];
-            a.minInc_all[off + x] = mi;
-            a.label_all[off + x] = lab;
+            VInfo vi;
+            vi.minInc = mi;
+            vi.label = lab;
+            a.vinfo_all[off + x] = vi;
             if (first && level0) {
                 int32_t vp = -1;
                 if (mi != kInf) {
@@ -487,8 +489,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     // last level: no edges left, every vertex is its component's root chain
     if (!(err & kErrOverflow) && off + n <= a.flat_cap) {
         for (int x = tid; x < n; x += kTailThreads) {
-            a.minInc_all[off + x] = kInf;
-            a.label_all[off + x] = -1;
+            VInfo vi;
+            vi.minInc = kInf;
+            vi.label = -1;
+            a.vinfo_all[off + x] = vi;
             if (first && level0) a.vertex_parent[x] = -1;
         }
     }

@@ -41,8 +41,9 @@ struct Layout {
     std::vector<int64_t> capE, capV;
     int64_t flat_cap = 0;
     int chain_passes = 0;
+    int chain_bits = 8;
     size_t ctrl, voff, K0, K1, V0, V1, perm, rank, E0, EA, EB, min64, own, alpha, scan_lb,
-        tile_excl, minInc, label, ptr, svflat, lb0, lb1;
+        tile_excl, vinfo, ptr, svflat, lb0, lb1;
     size_t total = 0;
 };
 
@@ -80,10 +81,13 @@ Layout make_layout(int64_t N, int32_t B) {
     const int64_t key_range = std::max<int64_t>(L.flat_cap - N, 1);
     int bits = 0;
     while ((int64_t(1) << bits) < key_range) ++bits;
-    L.chain_passes = std::max(1, (bits + kSortBits - 1) / kSortBits);
+    // Chain keys need `bits` bits: as few passes of 9-bit digits as cover
+    // them, with 8-bit digits whenever those cover the same pass count.
+    L.chain_passes = std::max(1, (bits + kMaxRadixBits - 1) / kMaxRadixBits);
+    L.chain_bits = (8 * L.chain_passes >= bits) ? 8 : 9;
 
     const int64_t E1 = std::max<int64_t>(L.capE[1], 1), E2 = std::max<int64_t>(L.capE[2], 1);
-    const int64_t sortlb = sort_tiles(std::max<int64_t>(M, 1)) * kRadix;
+    const int64_t sortlb = sort_tiles(std::max<int64_t>(M, 1)) * kMaxRadix;
     const int64_t scant = scan_tiles(std::max<int64_t>(M, 1));
     size_t c = 0;
     L.ctrl = take(c, sizeof(Control));
@@ -102,8 +106,7 @@ Layout make_layout(int64_t N, int32_t B) {
     L.alpha = take(c, M);
     L.scan_lb = take(c, 8 * scant);
     L.tile_excl = take(c, 4 * scant);
-    L.minInc = take(c, 4 * L.flat_cap);
-    L.label = take(c, 4 * L.flat_cap);
+    L.vinfo = take(c, sizeof(VInfo) * L.flat_cap);
     L.ptr = take(c, 4 * N);
     L.svflat = take(c, 4 * M);
     L.lb0 = take(c, 8 * sortlb);
@@ -312,10 +315,9 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     int32_t* V[2] = {at<int32_t>(d, L.V0), at<int32_t>(d, L.V1)};
     uint64_t* LB[2] = {at<uint64_t>(d, L.lb0), at<uint64_t>(d, L.lb1)};
     int32_t* perm = at<int32_t>(d, L.perm);
-    int32_t* minInc_all = at<int32_t>(d, L.minInc);
-    int32_t* label_all = at<int32_t>(d, L.label);
+    VInfo* vinfo_all = at<VInfo>(d, L.vinfo);
     int32_t* svflat = at<int32_t>(d, L.svflat);
-    const int64_t lb_words = sort_tiles(M) * kRadix;
+    const int64_t lb_words = sort_tiles(M) * kMaxRadix;
 
     PD_TIMED(PK_ZERO, sizeof(Control), launch_zero_control(ctrl, s));
 
@@ -326,6 +328,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     {
         SortHistArgs h{};
         h.n = M;
+        h.bits = 8;
         h.hist_row = 0;
         h.passes = 4;
         h.w = w;
@@ -342,7 +345,8 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         for (int p = 0; p < 4; ++p) {
             SortPassArgs a{};
             a.n = M;
-            a.shift = kSortBits * p;
+            a.bits = 8;
+            a.shift = 8 * p;
             a.pass = p;
             a.w = w;
             a.keys_in = kin;
@@ -382,8 +386,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         a.forest = forest;
         a.E = E;
         a.min64 = min64;
-        a.minInc = minInc_all + off;
-        a.label = label_all + off;
+        a.vinfo = vinfo_all + off;
         a.off_next = off + n;
         a.ptr = at<int32_t>(d, L.ptr);
         a.own = own;
@@ -437,8 +440,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         t.level0 = j == 0 ? 1 : 0;
         t.off = off;
         t.flat_cap = L.flat_cap;
-        t.minInc_all = minInc_all;
-        t.label_all = label_all;
+        t.vinfo_all = vinfo_all;
         t.svflat = svflat;
         t.perm = perm;
         t.vertex_parent = vertex_parent;
@@ -456,8 +458,8 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         wa.n0 = N;
         wa.flat_cap = L.flat_cap;
         wa.svflat = svflat;
-        wa.minInc_all = minInc_all;
-        wa.label_all = label_all;
+        wa.vinfo_all = vinfo_all;
+        wa.bits = L.chain_bits;
         wa.ckey = K[0];
         wa.hist_row = 4;
         wa.passes = L.chain_passes;
@@ -470,7 +472,8 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         for (int p = 0; p < L.chain_passes; ++p) {
             SortPassArgs a{};
             a.n = M;
-            a.shift = kSortBits * p;
+            a.bits = L.chain_bits;
+            a.shift = L.chain_bits * p;
             a.pass = 4 + p;
             a.keys_in = kin;
             a.vals_in = vin;
@@ -490,7 +493,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         sa.flat_cap = L.flat_cap;
         sa.skey = kin;
         sa.sid = vin;
-        sa.minInc_all = minInc_all;
+        sa.vinfo_all = vinfo_all;
         sa.perm = perm;
         sa.edge_parent = edge_parent;
         sa.forest = forest;

@@ -1,4 +1,4 @@
-// Stable LSD radix sort with 8-bit digits for gfx950.
+// Stable LSD radix sort with 8- or 9-bit digits for gfx950.
 //
 // Sorting is the first step of the method (the paper's Section 3.1.1 orders
 // the MST edges by weight with a consistent tie order) and it is used again
@@ -6,7 +6,7 @@
 // sort to a library; here it is a one-sweep radix sort:
 //
 //   * one histogram pass computes the digit counts of every pass at once;
-//   * each digit pass loads a 4096-key tile, ranks it stably inside LDS
+//   * each digit pass loads an 8192-key tile, ranks it stably inside LDS
 //     (wave64 ballot matching of digits, per-wave digit counters), publishes
 //     the tile's per-digit counts and resolves the global offsets with a
 //     decoupled look-back over earlier tiles (dynamic tile ids, so every tile
@@ -29,7 +29,7 @@ constexpr uint64_t kFlagMask = 3ull << 62;
 constexpr uint64_t kCountMask = ~kFlagMask;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-static_assert(kRadix == kSortBlock, "one digit per thread");
+static_assert(kSortBlock >= kMaxRadix, "threads below the radix own one digit each");
 
 // Exclusive scan of one value per thread across a block of BLOCK threads.
 template <int BLOCK>
@@ -49,8 +49,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wsum
 
 template <int SRC>
 __global__ __launch_bounds__(256) void k_sort_hist(SortHistArgs a) {
-    __shared__ uint32_t s_h[4][kRadix];
-    for (int i = threadIdx.x; i < 4 * kRadix; i += blockDim.x) (&s_h[0][0])[i] = 0;
+    __shared__ uint32_t s_h[4][kMaxRadix];
+    const int radix = 1 << a.bits;
+    const uint32_t mask = (uint32_t)radix - 1u;
+    for (int i = threadIdx.x; i < 4 * kMaxRadix; i += blockDim.x) (&s_h[0][0])[i] = 0;
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,22 +66,22 @@ __global__ __launch_bounds__(256) void k_sort_hist(SortHistArgs a) {
         } else {
             key = a.keys[i];
         }
-        for (int p = 0; p < a.passes; ++p)
-            atomicAdd(&s_h[p][(key >> (kSortBits * p)) & (kRadix - 1)], 1u);
+        for (int p = 0; p < a.passes; ++p) atomicAdd(&s_h[p][(key >> (a.bits * p)) & mask], 1u);
     }
     for (int64_t i = t0; i < a.fill_n; i += stride) a.fill64[i] = ~0ull;
     for (int64_t i = t0; i < a.zero_n; i += stride) a.zero32[i] = 0;
     for (int64_t i = t0; i < a.lb_zero_words; i += stride) a.lb_zero[i] = 0;
     if (SRC == SRC_WEIGHT && ballot(nan_seen) != 0 && lane_id() == 0) raise_err(a.ctrl, kErrNaN);
     __syncthreads();
-    for (int i = threadIdx.x; i < a.passes * kRadix; i += blockDim.x) {
-        const uint32_t c = (&s_h[0][0])[i];
-        if (c) atomicAdd(&a.ctrl->hist[a.hist_row + i / kRadix][i % kRadix], c);
+    for (int i = threadIdx.x; i < a.passes * radix; i += blockDim.x) {
+        const uint32_t c = s_h[i / radix][i % radix];
+        if (c) atomicAdd(&a.ctrl->hist[a.hist_row + i / radix][i % radix], c);
     }
 }
 
-template <int SRC, int DST>
+template <int BITS, int SRC, int DST>
 __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
+    constexpr int kRadix = 1 << BITS;
     constexpr int W = kSortBlock / kWave;
     __shared__ uint32_t s_cnt[W][kRadix];     // per-wave digit counters, then offsets
     __shared__ uint32_t s_start[kRadix];      // first local slot of each digit
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
         const uint32_t d = (key[k] >> a.shift) & (kRadix - 1);
         uint64_t peers = ballot(valid);
 #pragma unroll
-        for (int b = 0; b < kSortBits; ++b) {
+        for (int b = 0; b < BITS; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t mb = ballot(bit);
             peers &= bit ? mb : ~mb;
@@ -148,46 +150,51 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
     }
     __syncthreads();
 
-    // Thread d owns digit d: wave offsets, tile total, look-back.
-    const int d = tid;
+    // Thread d < kRadix owns digit d: wave offsets, tile total, look-back.
+    const bool owner = tid < kRadix;
+    const int d = owner ? tid : 0;
     uint32_t tot = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        const uint32_t c = s_cnt[w][d];
-        s_cnt[w][d] = tot;
-        tot += c;
-    }
     uint64_t* my = a.lb + tile * kRadix + d;
-    st_relaxed(my, (tile == 0 ? kFlagInc : kFlagAgg) | (uint64_t)tot);
+    if (owner) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint32_t c = s_cnt[w][d];
+            s_cnt[w][d] = tot;
+            tot += c;
+        }
+        st_relaxed(my, (tile == 0 ? kFlagInc : kFlagAgg) | (uint64_t)tot);
+    }
 
-    const uint32_t hist_d = a.ctrl->hist[a.pass][d];
+    const uint32_t hist_d = owner ? a.ctrl->hist[a.pass][d] : 0u;
     const uint32_t digit_off = block_excl_scan<kSortBlock>(hist_d, s_wsum);
     const uint32_t start = block_excl_scan<kSortBlock>(tot, s_wsum);
-    s_start[d] = start;
 
-    uint64_t excl = 0;
-    if (tile > 0) {
-        int64_t p = tile - 1;
-        uint32_t spins = 0;
-        while (true) {
-            const uint64_t wv = ld_relaxed(a.lb + p * kRadix + d);
-            const uint64_t flag = wv & kFlagMask;
-            if (flag == 0) {
-                if (++spins > kSpinLimit) {
-                    raise_err(a.ctrl, kErrSpin);
-                    break;
+    if (owner) {
+        s_start[d] = start;
+        uint64_t excl = 0;
+        if (tile > 0) {
+            int64_t p = tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const uint64_t wv = ld_relaxed(a.lb + p * kRadix + d);
+                const uint64_t flag = wv & kFlagMask;
+                if (flag == 0) {
+                    if (++spins > kSpinLimit) {
+                        raise_err(a.ctrl, kErrSpin);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
                 }
-                __builtin_amdgcn_s_sleep(1);
-                continue;
+                spins = 0;
+                excl += wv & kCountMask;
+                if (flag == kFlagInc || p == 0) break;
+                --p;
             }
-            spins = 0;
-            excl += wv & kCountMask;
-            if (flag == kFlagInc || p == 0) break;
-            --p;
+            st_relaxed(my, kFlagInc | (excl + tot));
         }
-        st_relaxed(my, kFlagInc | (excl + tot));
+        s_gbase[d] = (int64_t)digit_off + (int64_t)excl - (int64_t)start;
     }
-    s_gbase[d] = (int64_t)digit_off + (int64_t)excl - (int64_t)start;
     __syncthreads();
 
     // Place the tile in digit order in LDS.
@@ -237,14 +244,20 @@ hipError_t launch_sort_hist(int src, const SortHistArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int BITS>
+void launch_pass_bits(int src, int dst, const SortPassArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    if (src == SRC_WEIGHT && dst == DST_KEYS) k_sort_pass<BITS, SRC_WEIGHT, DST_KEYS><<<grid, block, 0, s>>>(a);
+    else if (src == SRC_WEIGHT) k_sort_pass<BITS, SRC_WEIGHT, DST_RANK><<<grid, block, 0, s>>>(a);
+    else if (dst == DST_KEYS) k_sort_pass<BITS, SRC_KEYS, DST_KEYS><<<grid, block, 0, s>>>(a);
+    else k_sort_pass<BITS, SRC_KEYS, DST_RANK><<<grid, block, 0, s>>>(a);
+}
+
 hipError_t launch_sort_pass(int src, int dst, const SortPassArgs& a, hipStream_t s) {
     const int64_t tiles = sort_tiles(a.n);
     if (tiles < 1) return hipSuccess;
     const dim3 grid((unsigned)tiles), block(kSortBlock);
-    if (src == SRC_WEIGHT && dst == DST_KEYS) k_sort_pass<SRC_WEIGHT, DST_KEYS><<<grid, block, 0, s>>>(a);
-    else if (src == SRC_WEIGHT) k_sort_pass<SRC_WEIGHT, DST_RANK><<<grid, block, 0, s>>>(a);
-    else if (dst == DST_KEYS) k_sort_pass<SRC_KEYS, DST_KEYS><<<grid, block, 0, s>>>(a);
-    else k_sort_pass<SRC_KEYS, DST_RANK><<<grid, block, 0, s>>>(a);
+    if (a.bits == 9) launch_pass_bits<9>(src, dst, a, grid, block, s);
+    else launch_pass_bits<8>(src, dst, a, grid, block, s);
     return hipGetLastError();
 }
 
