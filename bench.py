@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="also report every kernel kind's time")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture each call once into a HIP graph and replay it every step")
     ap.add_argument("--compare-per-tree", action="store_true",
                     help="c4: also time the same trees built one call per tree")
     ap.add_argument("--duration", type=float, default=20.0, help="c5: seconds of arrivals")
@@ -173,7 +175,19 @@ def main():
             total_vertices += obj.n_total
     torch.cuda.synchronize()
 
+    graphs = []
+    if args.graph:
+        for c in calls:
+            if c[0] == "tree":
+                graphs.append(pd.Graph(c[2], c[3], c[4], n=c[1]))
+            else:
+                graphs.append(pd.Graph(c[2], c[3], c[4], voff=c[1]))
+
     def step():
+        if graphs:
+            for g in graphs:
+                g.launch()
+            return
         for c in calls:
             if c[0] == "tree":
                 st = pd.dendrogram_into(*c[1:])
@@ -230,7 +244,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "edges_per_step": total_edges, "vertices_per_step": total_vertices,
-                   "calls_per_step": len(calls), "parallelism": "single GPU"},
+                   "calls_per_step": len(calls), "parallelism": "single GPU",
+                   "hip_graph": bool(args.graph), "tuning": pd.get_tuning()},
         "mpoints_per_s": total_vertices * args.steps / elapsed / 1e6,
         "last_call_stats": pd.last_stats(),
         "latency_ms": {"p50": 1000 * statistics.median(lat),

@@ -90,8 +90,27 @@ size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B);
 /* Per-stage statistics of the last successful call on this thread:
  * out[0] = levels, out[1] = sum of edges over all levels, out[2] = pointer
  * jumping launches, out[3] = levels done in the LDS tail, out[4] = edges at
- * the level the LDS tail started from.  Returns the number filled (<= cap). */
+ * the level the LDS tail started from, out[5] = 1 if the call ran without
+ * host round trips.  Returns the number filled (<= cap). */
 int pandora_last_stats(int64_t* out, int cap);
+
+/* Process-wide tuning knobs (defaults in brackets), read at the start of
+ * every call.  They change speed only, never results.
+ *   sync_free_max_edges  calls with at most this many edges run their level
+ *                        loop without host round trips: grids sized by the
+ *                        level bounds, empty levels return at once [0]
+ *   jump_steps           pointer-jumping steps per thread per launch [16]
+ *   chain_digit_bits     radix digit width of the chain sort: 8, 9, or 0 for
+ *                        8 [0]
+ * pandora_set_tuning returns INVALID_ARG for out-of-range values. */
+typedef struct {
+    int32_t sync_free_max_edges;
+    int32_t jump_steps;
+    int32_t chain_digit_bits;
+    int32_t reserved;
+} pandora_tuning_t;
+int pandora_set_tuning(const pandora_tuning_t* t);
+int pandora_get_tuning(pandora_tuning_t* t);
 
 /* Per-kernel profiler (tracing).  pandora_profile_enable(mask) clears the
  * counters and, for every kernel kind k with bit k set in mask, brackets each
@@ -103,6 +122,25 @@ int pandora_last_stats(int64_t* out, int cap);
 int pandora_profile_enable(uint32_t kind_mask);
 int pandora_profile_read(double* ms, double* bytes, int64_t* launches, int cap);
 const char* pandora_profile_name(int kind);
+
+/* Captured calls (HIP graphs).  pandora_graph_create captures the whole
+ * method for fixed arguments -- the same pointers and sizes as
+ * pandora_dendrogram -- into a HIP graph with its own scratch memory (the
+ * level loop runs in its sync-free form, so nothing waits for the device
+ * inside the graph).  pandora_graph_launch replays it on hip_stream, waits
+ * for it and returns the call's status; the arrays must hold the inputs
+ * when it is launched.  Replays of one graph must not overlap.  The batched
+ * form takes the same arguments as pandora_dendrogram_batched (voff is
+ * copied at creation).  pandora_graph_destroy frees the graph and its
+ * memory. */
+typedef struct pandora_graph pandora_graph_t;
+int pandora_graph_create(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                         int32_t* edge_parent, int32_t* vertex_parent, pandora_graph_t** out);
+int pandora_graph_create_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
+                                 const float* w, int32_t* edge_parent, int32_t* vertex_parent,
+                                 pandora_graph_t** out);
+int pandora_graph_launch(pandora_graph_t* g, void* hip_stream);
+void pandora_graph_destroy(pandora_graph_t* g);
 
 /* Free every cached scratch allocation (waits for the owning streams). */
 void pandora_release_workspaces(void);

@@ -39,6 +39,15 @@ class PandoraError(RuntimeError):
 _lib = None
 
 
+class Tuning(ctypes.Structure):
+    """Mirror of pandora_tuning_t (speed knobs only; results never change)."""
+    _fields_ = [("sync_free_max_edges", ctypes.c_int32), ("jump_steps", ctypes.c_int32),
+                ("chain_digit_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -64,6 +73,19 @@ def _load():
     lib.pandora_profile_read.restype = ctypes.c_int
     lib.pandora_profile_name.argtypes = [ctypes.c_int]
     lib.pandora_profile_name.restype = ctypes.c_char_p
+    lib.pandora_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.pandora_set_tuning.restype = ctypes.c_int
+    lib.pandora_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.pandora_get_tuning.restype = ctypes.c_int
+    lib.pandora_graph_create.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_void_p)]
+    lib.pandora_graph_create.restype = ctypes.c_int
+    lib.pandora_graph_create_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp,
+                                                 ctypes.POINTER(ctypes.c_void_p)]
+    lib.pandora_graph_create_batched.restype = ctypes.c_int
+    lib.pandora_graph_launch.argtypes = [vp, vp]
+    lib.pandora_graph_launch.restype = ctypes.c_int
+    lib.pandora_graph_destroy.argtypes = [vp]
+    lib.pandora_graph_destroy.restype = None
     lib.pandora_status_string.argtypes = [ctypes.c_int]
     lib.pandora_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -165,10 +187,24 @@ def workspace_bytes(n_total_vertices: int, trees: int = 1) -> int:
 
 
 def last_stats() -> dict:
-    buf = (ctypes.c_int64 * 5)()
-    k = _load().pandora_last_stats(buf, 5)
-    names = ["levels", "sum_level_edges", "jump_launches", "tail_levels", "tail_entry_edges"]
+    buf = (ctypes.c_int64 * 6)()
+    k = _load().pandora_last_stats(buf, 6)
+    names = ["levels", "sum_level_edges", "jump_launches", "tail_levels", "tail_entry_edges", "sync_free"]
     return {names[i]: int(buf[i]) for i in range(k)}
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(_load().pandora_get_tuning(ctypes.byref(t)))
+    return t.as_dict()
+
+
+def set_tuning(**kw) -> dict:
+    """Update process-wide tuning knobs; returns the previous values."""
+    old = get_tuning()
+    t = Tuning(**{**old, **kw})
+    _check(_load().pandora_set_tuning(ctypes.byref(t)))
+    return old
 
 
 def release_workspaces():
@@ -194,3 +230,58 @@ def profile_read() -> dict:
     k = lib.pandora_profile_read(ms, by, ln, cap)
     return {lib.pandora_profile_name(i).decode(): {"kind": i, "ms": ms[i], "bytes": by[i], "launches": int(ln[i])}
             for i in range(k)}
+
+
+class Graph:
+    """A dendrogram call captured once into a HIP graph and replayed.
+
+    The inputs (device tensors u, v, w; host offsets voff for a forest) are
+    bound at creation; replace their contents in place and call launch() to
+    build the dendrogram of the new data.  Outputs live in edge_parent and
+    vertex_parent.  Replays must not overlap.
+    """
+
+    def __init__(self, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, n: Optional[int] = None,
+                 voff=None):
+        lib = _load()
+        self._h = ctypes.c_void_p()
+        dev = w.device
+        self.u = _as_dev(u, torch.int32, dev)
+        self.v = _as_dev(v, torch.int32, dev)
+        self.w = _as_dev(w, torch.float32, dev)
+        m = w.numel()
+        with torch.cuda.device(dev):
+            if voff is None:
+                n = m + 1 if n is None else int(n)
+                if n != m + 1:
+                    raise ValueError("a tree with n vertices has n-1 edges")
+                self.edge_parent = torch.empty(m, dtype=torch.int32, device=dev)
+                self.vertex_parent = torch.empty(n, dtype=torch.int32, device=dev)
+                st = lib.pandora_graph_create(n, _dptr(self.u), _dptr(self.v), _dptr(self.w),
+                                              _dptr(self.edge_parent), _dptr(self.vertex_parent),
+                                              ctypes.byref(self._h))
+            else:
+                self.voff = torch.as_tensor(voff, dtype=torch.int64).cpu().contiguous()
+                B = self.voff.numel() - 1
+                N = int(self.voff[-1])
+                self.edge_parent = torch.empty(N - B, dtype=torch.int32, device=dev)
+                self.vertex_parent = torch.empty(N, dtype=torch.int32, device=dev)
+                st = lib.pandora_graph_create_batched(
+                    B, ctypes.c_void_p(self.voff.data_ptr()), _dptr(self.u), _dptr(self.v), _dptr(self.w),
+                    _dptr(self.edge_parent), _dptr(self.vertex_parent), ctypes.byref(self._h))
+        _check(st)
+
+    def launch(self, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+        _check(_load().pandora_graph_launch(self._h, _stream_handle(stream)))
+        return self.edge_parent, self.vertex_parent
+
+    def close(self):
+        if self._h:
+            _load().pandora_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,6 +18,14 @@ enum : uint32_t {
     kErrWalk = 1u << 5,       // the expansion walk left the level tables
 };
 
+// Sizes of one contraction level, written on the device by the level before
+// it: m edges, n vertices, flat offset of its vertex table.
+struct LevelInfo {
+    int32_t m, n;
+    int64_t off;
+};
+constexpr int kMaxLevels = 40;   // > ceil(log2(2^31)) + 2
+
 // Device-resident control block; zeroed at the start of every call.
 struct Control {
     uint32_t err;
@@ -29,6 +37,7 @@ struct Control {
     int32_t tail_levels;      // levels finished inside the LDS tail kernel
     int32_t tail_vertices;    // vertices of the last level (all isolated)
     uint32_t sort_tiles[8];   // dynamic tile counters, one per radix pass
+    LevelInfo lv[kMaxLevels]; // level sizes (lv[0] set at the start of a call)
     uint32_t hist[8][512];    // per-pass digit histograms (8- or 9-bit digits)
 };
 

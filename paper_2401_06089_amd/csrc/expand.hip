@@ -76,10 +76,16 @@ __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
     a.edge_parent[id] = parent;
 }
 
-__global__ void k_zero_control(Control* c) {
+__global__ void k_zero_control(Control* c, int32_t m, int32_t n) {
     uint32_t* p = reinterpret_cast<uint32_t*>(c);
     const int words = (int)(sizeof(Control) / sizeof(uint32_t));
     for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c->lv[0].m = m;
+        c->lv[0].n = n;
+        c->lv[0].off = 0;
+    }
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t value) {
@@ -103,8 +109,8 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_zero_control(Control* c, hipStream_t s) {
-    k_zero_control<<<1, 256, 0, s>>>(c);
+hipError_t launch_zero_control(Control* c, int32_t m, int32_t n, hipStream_t s) {
+    k_zero_control<<<1, 256, 0, s>>>(c, m, n);
     return hipGetLastError();
 }
 

@@ -85,17 +85,22 @@ struct alignas(8) VInfo {
 constexpr uint64_t kNoEdge = ~0ull;          // min64 of a vertex without edges
 constexpr int32_t kLabelFlag = INT32_MIN;    // ptr word holding a final label
 
+// Level kernels read their sizes from Control::lv[level] on the device, so a
+// level can be launched before the host knows how large it is; grids are
+// sized by the capacities below and surplus threads return at once.  A level
+// that fits the LDS tail (or is empty) is left to k_tail: all its kernels
+// return immediately.
 struct LevelArgs {
-    int32_t m;                 // edges at this level
-    int32_t n;                 // vertices at this level
+    int level;
+    int32_t cap_m;             // edge capacity of this level's buffers (grid size)
+    int32_t cap_n;             // vertex capacity of this level
     const int32_t* in_u;       // level 0: caller's endpoints (tree-local ids)
     const int32_t* in_v;
     const int32_t* rank;       // level 0: rank of each input edge
     Forest forest;
     EdgeRec* E;                // this level's edges (level 0: written by k_min_incident)
     uint64_t* min64;           // per vertex: (rank << 32) | position of its lightest edge
-    VInfo* vinfo;              // flat table + off_j
-    int64_t off_next;          // flat offset of level j+1
+    VInfo* vinfo_all;          // flat per-vertex table of all levels
     int32_t* ptr;              // contraction pointers / final labels (kLabelFlag set)
     uint16_t* own;             // per edge: byte 0 = owned by u, byte 1 = owned by v
     uint8_t* alpha;            // per-edge alpha flag
@@ -111,6 +116,10 @@ struct LevelArgs {
     int round;
 };
 
+__host__ __device__ inline bool tail_level(int64_t m, int64_t n, int tail_e, int tail_v) {
+    return m == 0 || (m <= tail_e && n <= tail_v);
+}
+
 hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s);
 hipError_t launch_own(bool level0, const LevelArgs& a, hipStream_t s);
 hipError_t launch_classify(const LevelArgs& a, hipStream_t s);
@@ -123,14 +132,11 @@ constexpr int kTailE = 4096;
 constexpr int kTailV = 8192;
 
 struct TailArgs {
-    int32_t m;
-    int32_t n;
-    const EdgeRec* E;          // entry level edges (levels >= 1)
+    const EdgeRec* EA;         // level edges of odd levels
+    const EdgeRec* EB;         // level edges of even levels >= 2
     const int32_t* in_u;       // level-0 entry: caller's endpoints and ranks
     const int32_t* in_v;
     const int32_t* rank;
-    int level0;
-    int64_t off;               // flat offset of the entry level
     int64_t flat_cap;
     VInfo* vinfo_all;
     int32_t* svflat;
@@ -174,7 +180,7 @@ hipError_t launch_walk_hist(const WalkArgs& a, hipStream_t s);
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t s);
 
 // ---- misc -----------------------------------------------------------------------
-hipError_t launch_zero_control(Control* c, hipStream_t s);
+hipError_t launch_zero_control(Control* c, int32_t m, int32_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s);
 
 }  // namespace pandora

@@ -33,8 +33,13 @@
 // [off_j, off_j + n_j).  Isolated vertices (finished components of a forest)
 // are not carried to the next level.
 //
+// Sizes come from Control::lv on the device (the previous level's k_classify
+// writes them), clamped to the buffers' capacities, so the same kernels serve
+// a host loop that reads the sizes back and a fixed launch sequence with no
+// host round trip at all.
+//
 // k_tail runs every remaining level inside one workgroup's LDS once a level
-// is small, replacing ~5 launches and one host round trip per level.
+// is small, replacing ~5 launches per level.
 #include "kernels.hpp"
 
 namespace pandora {
@@ -48,15 +53,36 @@ constexpr uint64_t kCountMask = ~kFlagMask;
 constexpr uint64_t kLow31 = (1ull << 31) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
+struct LevelView {
+    int32_t m, n;
+    int64_t off, off_next;
+    bool skip;   // empty, or small enough for the LDS tail
+};
+
+__device__ __forceinline__ LevelView level_view(const LevelArgs& a) {
+    const LevelInfo L = a.ctrl->lv[a.level];
+    LevelView v;
+    v.m = L.m < a.cap_m ? L.m : a.cap_m;
+    v.n = L.n < a.cap_n ? L.n : a.cap_n;
+    v.off = L.off;
+    v.off_next = L.off + v.n;
+    v.skip = tail_level(v.m, v.n, kTailE, kTailV);
+    return v;
+}
+
+// After an input error every level kernel returns at once: the call's outputs
+// are unspecified then, and nothing may index with the damaged tables.
 template <bool L0>
 __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
+    const LevelView L = level_view(a);
+    if (L.skip || a.ctrl->err) return;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < scan_tiles(a.m)) a.scan_lb[i] = 0;
+    if (i < scan_tiles(L.m)) a.scan_lb[i] = 0;
     if (i == 0) {
         a.ctrl->alpha_tiles = 0;
         a.ctrl->not_converged = 0;
     }
-    if (i >= a.m) return;
+    if (i >= L.m) return;
     EdgeRec e;
     if (L0) {
         const int32_t b = a.forest.tree_of_edge(i);
@@ -86,24 +112,31 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
 
 template <bool L0>
 __global__ __launch_bounds__(256) void k_own(LevelArgs a) {
+    const LevelView L = level_view(a);
+    if (L.skip || a.ctrl->err) return;
+    VInfo* vinfo = a.vinfo_all + L.off;
     const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool live = x < a.n;
+    const bool live = x < L.n;
     const uint64_t mm = live ? a.min64[x] : 0;
     const bool isolated = live && mm == kNoEdge;
     const uint64_t b = ballot(isolated);
     if (b != 0 && lane_id() == __ffsll((long long)b) - 1) atomicAdd(&a.ctrl->isolated, (uint32_t)popc64(b));
     if (!live) return;
     if (isolated) {
-        a.vinfo[x].minInc = kInf;
+        vinfo[x].minInc = kInf;
         if (L0) a.vertex_parent[x] = -1;
         return;
     }
     const uint32_t pos = (uint32_t)mm;
+    if (pos >= (uint32_t)L.m) {
+        raise_err(a.ctrl, kErrOverflow);
+        return;
+    }
     const EdgeRec e = a.E[pos];
     const int side = (e.u == (int32_t)x) ? 0 : 1;
     a.ptr[x] = side ? e.u : e.v;
     reinterpret_cast<uint8_t*>(a.own)[2 * (int64_t)pos + side] = 1;
-    a.vinfo[x].minInc = (int32_t)(mm >> 32);
+    vinfo[x].minInc = (int32_t)(mm >> 32);
     if (L0) {
         int32_t vp = e.id;
         if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex(x)));
@@ -117,10 +150,15 @@ __global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
     __shared__ uint32_t s_cl[kScanItems][W];
     __shared__ uint64_t s_excl;
     __shared__ uint32_t s_tile;
+    const LevelView L = level_view(a);
+    // The error check comes before a tile is claimed: a claimed tile is always
+    // finished, so no claimed tile ever waits on a tile that nobody claimed.
+    if (L.skip || a.ctrl->err) return;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     if (tid == 0) s_tile = atomicAdd(&a.ctrl->alpha_tiles, 1u);
     __syncthreads();
     const int64_t tile = s_tile;
+    if (tile >= scan_tiles(L.m)) return;       // surplus workgroup of a capacity-sized grid
     const int64_t base = tile * kScanTile;
     const uint64_t lt = lanemask_lt();
 
@@ -133,7 +171,7 @@ __global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
         const int64_t idx = base + k * kScanBlock + tid;
         bool al = false, lf = false;
         root[k] = 0;
-        if (idx < a.m) {
+        if (idx < L.m) {
             const uint16_t o = a.own[idx];
             a.own[idx] = 0;
             const EdgeRec e = a.E[idx];
@@ -191,10 +229,24 @@ __global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
         }
         s_excl = excl;
         a.tile_alpha_excl[tile] = (int32_t)(excl >> 31);
-        if (tile == scan_tiles(a.m) - 1) {
+        if (tile == scan_tiles(L.m) - 1) {
             const uint64_t all = excl + agg;
-            a.ctrl->m_next = (int32_t)(all >> 31);
-            a.ctrl->n_next = (int32_t)(all & kLow31);
+            int32_t mn = (int32_t)(all >> 31), nn = (int32_t)(all & kLow31);
+            a.ctrl->m_next = mn;
+            a.ctrl->n_next = nn;
+            // Section 4.2 bounds the next level; a larger one is not a tree.
+            if (mn > a.cap_next_e || nn > a.cap_next_v || mn >= L.m) {
+                raise_err(a.ctrl, kErrOverflow);
+                mn = 0;
+                nn = 0;
+            }
+            if (a.level + 1 < kMaxLevels) {
+                LevelInfo nx;
+                nx.m = mn;
+                nx.n = nn;
+                nx.off = L.off_next;
+                a.ctrl->lv[a.level + 1] = nx;
+            }
         }
     }
     __syncthreads();
@@ -209,16 +261,22 @@ __global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
+    const LevelView L = level_view(a);
+    if (L.skip) return;
+    // a later round runs only if the previous one left some vertex unresolved
+    if (a.round > 0 && !(a.ctrl->not_converged & (1u << ((a.round - 1) & 31)))) return;
+    if (a.ctrl->err) return;                     // invalid input: outputs are unspecified
+    VInfo* vinfo = a.vinfo_all + L.off;
     const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (x >= a.n) return;
+    if (x >= L.n) return;
     if (a.round == 0) {
-        int32_t nn = a.ctrl->n_next;
+        int32_t nn = a.ctrl->lv[a.level + 1].n;
         if (nn > a.cap_next_v) nn = a.cap_next_v;
         if (x < nn) a.min64[x] = kNoEdge;     // the next level starts clean
     }
-    const int32_t r = a.vinfo[x].minInc;
+    const int32_t r = vinfo[x].minInc;
     if (r == kInf) {
-        if (a.round == 0) a.vinfo[x].label = -1;
+        if (a.round == 0) vinfo[x].label = -1;
         return;
     }
     int32_t q = a.ptr[x];
@@ -239,16 +297,20 @@ __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
         lab = t & ~kLabelFlag;
         a.ptr[x] = t;                            // x now holds its label directly
     }
-    const int32_t flat = (int32_t)(a.off_next + lab);
-    a.vinfo[x].label = flat;
+    const int32_t flat = (int32_t)(L.off_next + lab);
+    vinfo[x].label = flat;
     a.svflat[r] = flat;                          // the lightest edge of x falls into this supervertex
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
     constexpr int W = kScanBlock / kWave;
     __shared__ uint32_t s_ca[kScanItems][W];
+    const LevelView L = level_view(a);
+    if (L.skip || a.ctrl->err) return;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     const int64_t tile = blockIdx.x;
+    if (tile >= scan_tiles(L.m)) return;
+    const VInfo* vinfo = a.vinfo_all + L.off;
     const int64_t base = tile * kScanTile;
     const uint64_t lt = lanemask_lt();
     uint32_t amask = 0;
@@ -256,7 +318,7 @@ __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t idx = base + k * kScanBlock + tid;
-        const bool al = idx < a.m && a.alpha[idx] != 0;
+        const bool al = idx < L.m && a.alpha[idx] != 0;
         const uint64_t ba = ballot(al);
         apre[k] = (uint32_t)popc64(ba & lt);
         amask |= (al ? 1u : 0u) << k;
@@ -280,14 +342,14 @@ __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
         if (!(amask & (1u << k))) continue;
         const int64_t idx = base + k * kScanBlock + tid;
         const EdgeRec e = a.E[idx];
-        const int32_t lx = a.vinfo[e.u].label;
-        const int32_t ly = a.vinfo[e.v].label;
+        const int32_t lx = vinfo[e.u].label;
+        const int32_t ly = vinfo[e.v].label;
         const int64_t pos = abase + s_ca[k][wave] + apre[k];
         selfloop |= lx == ly;
         if (pos < a.cap_next_e) {
             EdgeRec o;
-            o.u = (int32_t)(lx - a.off_next);
-            o.v = (int32_t)(ly - a.off_next);
+            o.u = (int32_t)(lx - L.off_next);
+            o.v = (int32_t)(ly - L.off_next);
             o.r = e.r;
             o.id = 0;
             a.out[pos] = o;
@@ -328,10 +390,21 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     __shared__ uint32_t s_wsum[kTailThreads / kWave];
     __shared__ uint32_t s_flag;
     const int tid = threadIdx.x;
-    const bool level0 = a.level0 != 0;
 
-    int32_t m = a.m, n = a.n;
-    int64_t off = a.off;
+    if (a.ctrl->err) return;
+    // Entry: the first level that is empty or fits in LDS.
+    int entry = 0;
+    while (entry + 1 < kMaxLevels && !tail_level(a.ctrl->lv[entry].m, a.ctrl->lv[entry].n, kTailE, kTailV))
+        ++entry;
+    const LevelInfo E0 = a.ctrl->lv[entry];
+    const bool level0 = entry == 0;
+    const EdgeRec* ent = (entry % 2 == 1) ? a.EA : a.EB;
+    int32_t m = E0.m, n = E0.n;
+    int64_t off = E0.off;
+    if (!tail_level(m, n, kTailE, kTailV) || off + (m > 0 ? n : 0) > a.flat_cap) {
+        if (tid == 0) raise_err(a.ctrl, kErrOverflow);
+        return;
+    }
     bool first = true;
     int levels = 0;
     uint32_t err = 0;
@@ -350,7 +423,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
             s_v[i] = (int32_t)(v0 + y);
             s_r[i] = a.rank[i];
         } else {
-            const EdgeRec e = a.E[i];
+            const EdgeRec e = ent[i];
             s_u[i] = e.u;
             s_v[i] = e.v;
             s_r[i] = e.r;
@@ -512,30 +585,30 @@ inline unsigned blocks_for(int64_t n, int per) {
 }  // namespace
 
 hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s) {
-    const int64_t work = a.m > scan_tiles(a.m) ? a.m : scan_tiles(a.m);
+    const int64_t work = a.cap_m > scan_tiles(a.cap_m) ? a.cap_m : scan_tiles(a.cap_m);
     if (level0) k_min_incident<true><<<blocks_for(work, 256), 256, 0, s>>>(a);
     else k_min_incident<false><<<blocks_for(work, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_own(bool level0, const LevelArgs& a, hipStream_t s) {
-    if (level0) k_own<true><<<blocks_for(a.n, 256), 256, 0, s>>>(a);
-    else k_own<false><<<blocks_for(a.n, 256), 256, 0, s>>>(a);
+    if (level0) k_own<true><<<blocks_for(a.cap_n, 256), 256, 0, s>>>(a);
+    else k_own<false><<<blocks_for(a.cap_n, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_classify(const LevelArgs& a, hipStream_t s) {
-    k_classify<<<(unsigned)scan_tiles(a.m), kScanBlock, 0, s>>>(a);
+    k_classify<<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_jump(const LevelArgs& a, hipStream_t s) {
-    k_jump<<<blocks_for(a.n, 256), 256, 0, s>>>(a);
+    k_jump<<<blocks_for(a.cap_n, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_compact(const LevelArgs& a, hipStream_t s) {
-    k_compact<<<(unsigned)scan_tiles(a.m), kScanBlock, 0, s>>>(a);
+    k_compact<<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 

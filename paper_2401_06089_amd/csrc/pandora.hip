@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -29,10 +30,25 @@
 namespace pandora {
 namespace {
 
-constexpr int kJumpSteps = 16;
 constexpr int kMaxJumpRounds = 64;
+constexpr int kSyncFreeJumpRounds = 3;   // the last one is bounded only by the level size
 constexpr size_t kAlign = 256;
 constexpr size_t kCtrlReadback = 32;   // err .. tail_vertices
+constexpr size_t kCtrlLevelsReadback = offsetof(Control, hist);   // header + level table
+
+// Process-wide tuning (pandora_set_tuning); read once per call.
+std::mutex g_tune_mu;
+pandora_tuning_t g_tune = {
+    /*sync_free_max_edges=*/0,
+    /*jump_steps=*/16,
+    /*chain_digit_bits=*/0,
+    /*reserved=*/0,
+};
+
+pandora_tuning_t current_tuning() {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return g_tune;
+}
 
 struct Layout {
     int64_t N = 0, M = 0;
@@ -59,7 +75,7 @@ int ceil_log2(int64_t x) {   // smallest L with 2^L >= x (x >= 1)
     return L;
 }
 
-Layout make_layout(int64_t N, int32_t B) {
+Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0) {
     Layout L;
     L.N = N;
     L.B = B;
@@ -83,8 +99,13 @@ Layout make_layout(int64_t N, int32_t B) {
     while ((int64_t(1) << bits) < key_range) ++bits;
     // Chain keys need `bits` bits: as few passes of 9-bit digits as cover
     // them, with 8-bit digits whenever those cover the same pass count.
-    L.chain_passes = std::max(1, (bits + kMaxRadixBits - 1) / kMaxRadixBits);
-    L.chain_bits = (8 * L.chain_passes >= bits) ? 8 : 9;
+    if (chain_bits_pref == 8 || chain_bits_pref == 9) {
+        L.chain_bits = chain_bits_pref;
+        L.chain_passes = std::max(1, (bits + chain_bits_pref - 1) / chain_bits_pref);
+    } else {
+        L.chain_bits = 8;
+        L.chain_passes = std::max(1, (bits + 7) / 8);
+    }
 
     const int64_t E1 = std::max<int64_t>(L.capE[1], 1), E2 = std::max<int64_t>(L.capE[2], 1);
     const int64_t sortlb = sort_tiles(std::max<int64_t>(M, 1)) * kMaxRadix;
@@ -128,7 +149,8 @@ std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
 
 struct Stats {
-    int64_t levels = 0, sum_edges = 0, jump_launches = 0, tail_levels = 0, tail_entry_edges = 0;
+    int64_t levels = 0, sum_edges = 0, jump_launches = 0, tail_levels = 0, tail_entry_edges = 0,
+            sync_free = 0;
 };
 thread_local Stats g_last;
 
@@ -177,12 +199,14 @@ hipEvent_t pooled_event() {
     return e;
 }
 
+thread_local bool t_capturing = false;   // no profiler events inside a graph capture
+
 template <class F>
 hipError_t timed(int kind, double bytes, hipStream_t s, F&& launch) {
     uint32_t mask;
     {
         std::lock_guard<std::mutex> g(g_prof.mu);
-        mask = g_prof.mask;
+        mask = t_capturing ? 0u : g_prof.mask;
     }
     if (!(mask & (1u << kind))) return launch();
     hipEvent_t a = pooled_event(), b = pooled_event();
@@ -274,38 +298,34 @@ T* at(void* base, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(base) + off);
 }
 
-int read_ctrl(Workspace& ws, Control* dctrl, Control* hctrl, hipStream_t s) {
-    PD_TRY(hipMemcpyAsync(hctrl, dctrl, kCtrlReadback, hipMemcpyDeviceToHost, s));
+int read_ctrl(Control* dctrl, Control* hctrl, hipStream_t s, size_t bytes = kCtrlReadback) {
+    PD_TRY(hipMemcpyAsync(hctrl, dctrl, bytes, hipMemcpyDeviceToHost, s));
     PD_TRY(hipStreamSynchronize(s));
-    (void)ws;
     return PANDORA_OK;
 }
 
-// The whole path for a forest described by host offsets voff[0..B].
-int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, const float* w,
-        int32_t* edge_parent, int32_t* vertex_parent, hipStream_t s) {
-    const int64_t N = voff[B];
-    const int64_t M = N - B;
-    Stats st;
-    if (M == 0) {   // only single-vertex trees: every vertex is a root
-        PD_TRY(launch_fill_i32(vertex_parent, N, -1, s));
-        PD_TRY(hipStreamSynchronize(s));
-        g_last = st;
-        return PANDORA_OK;
-    }
-    int dev = 0;
-    PD_TRY(hipGetDevice(&dev));
-    Workspace& ws = *workspace_for(dev, s);
-    std::lock_guard<std::mutex> lock(ws.mu);
-    const Layout L = make_layout(N, B);
-    const size_t host_bytes = sizeof(Control) + sizeof(int64_t) * (B + 1);
-    int rc = ensure(ws, L.total, host_bytes);
-    if (rc != PANDORA_OK) return rc;
+// One call's memory: the device scratch block and the pinned host block
+// (Control readback, then voff staging).
+struct Scratch {
+    void* dev;
+    void* host;
+};
 
-    void* d = ws.dev;
+size_t host_bytes_for(int32_t B) { return sizeof(Control) + sizeof(int64_t) * (B + 1); }
+
+// Enqueues the whole method for a forest given by host offsets voff[0..B]
+// (M >= 1 edges).  With sync_free nothing waits for the device before the
+// final readback in finish(), so the sequence can be captured in a graph.
+int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bool sync_free,
+            const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, const float* w,
+            int32_t* edge_parent, int32_t* vertex_parent, hipStream_t s, Stats& st) {
+    const int64_t N = L.N;
+    const int64_t M = L.M;
+    int rc = PANDORA_OK;
+    void* d = sc.dev;
     Control* ctrl = at<Control>(d, L.ctrl);
-    Control* hctrl = static_cast<Control*>(ws.host);
-    int64_t* hvoff = reinterpret_cast<int64_t*>(static_cast<char*>(ws.host) + sizeof(Control));
+    Control* hctrl = static_cast<Control*>(sc.host);
+    int64_t* hvoff = reinterpret_cast<int64_t*>(static_cast<char*>(sc.host) + sizeof(Control));
     std::memcpy(hvoff, voff, sizeof(int64_t) * (B + 1));
     int64_t* dvoff = at<int64_t>(d, L.voff);
     PD_TRY(hipMemcpyAsync(dvoff, hvoff, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
@@ -319,7 +339,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     int32_t* svflat = at<int32_t>(d, L.svflat);
     const int64_t lb_words = sort_tiles(M) * kMaxRadix;
 
-    PD_TIMED(PK_ZERO, sizeof(Control), launch_zero_control(ctrl, s));
+    PD_TIMED(PK_ZERO, sizeof(Control), launch_zero_control(ctrl, (int32_t)M, (int32_t)N, s));
 
     // ---- 1. weight sort --------------------------------------------------------
     uint64_t* min64 = at<uint64_t>(d, L.min64);
@@ -370,75 +390,96 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     EdgeRec* E0 = at<EdgeRec>(d, L.E0);
     EdgeRec* EA = at<EdgeRec>(d, L.EA);
     EdgeRec* EB = at<EdgeRec>(d, L.EB);
-    EdgeRec* E = E0;
-    int64_t m = M, n = N, off = 0;
-    int j = 0;
-    while (m > 0 && (m > kTailE || n > kTailV)) {
-        if (j >= L.Lmax) return PANDORA_ERR_NOT_A_TREE;
-        const bool l0 = j == 0;
-        EdgeRec* out = (j % 2 == 0) ? EA : EB;
+    const int jump_steps = tune.jump_steps > 0 ? tune.jump_steps : 16;
+    auto level_args = [&](int j) {
         LevelArgs a{};
-        a.m = (int32_t)m;
-        a.n = (int32_t)n;
+        a.level = j;
+        a.cap_m = (int32_t)L.capE[j];
+        a.cap_n = (int32_t)L.capV[j];
         a.in_u = u;
         a.in_v = v;
         a.rank = rank;
         a.forest = forest;
-        a.E = E;
+        a.E = j == 0 ? E0 : (j % 2 == 1 ? EA : EB);
+        a.out = j % 2 == 0 ? EA : EB;
         a.min64 = min64;
-        a.vinfo = vinfo_all + off;
-        a.off_next = off + n;
+        a.vinfo_all = vinfo_all;
         a.ptr = at<int32_t>(d, L.ptr);
         a.own = own;
         a.alpha = at<uint8_t>(d, L.alpha);
         a.scan_lb = at<uint64_t>(d, L.scan_lb);
         a.tile_alpha_excl = at<int32_t>(d, L.tile_excl);
-        a.out = out;
         a.cap_next_e = (int32_t)L.capE[j + 1];
         a.cap_next_v = (int32_t)L.capV[j + 1];
         a.svflat = svflat;
         a.vertex_parent = vertex_parent;
         a.ctrl = ctrl;
-        a.jump_steps = kJumpSteps;
-        PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 28.0 : 12.0) * m + 8.0 * n,
-                 launch_min_incident(l0, a, s));
-        PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 28.0 : 24.0) * n, launch_own(l0, a, s));
-        PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 21.0 * m,
-                 launch_classify(a, s));
-        for (int round = 0;; ++round) {
-            if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
-            a.round = round;
-            PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 24.0 : 16.0) * n, launch_jump(a, s));
-            ++st.jump_launches;
-            rc = read_ctrl(ws, ctrl, hctrl, s);
-            if (rc != PANDORA_OK) return rc;
-            if (hctrl->err) return status_from_err(hctrl->err);
-            if (!(hctrl->not_converged & (1u << (round & 31)))) break;
+        a.jump_steps = jump_steps;
+        return a;
+    };
+    st.sync_free = sync_free ? 1 : 0;
+    if (!sync_free) {
+        // Host-driven: exact grids, pointer jumping relaunched until it converges.
+        int64_t m = M, n = N;
+        int j = 0;
+        while (!tail_level(m, n, kTailE, kTailV)) {
+            if (j >= L.Lmax) return PANDORA_ERR_NOT_A_TREE;
+            const bool l0 = j == 0;
+            LevelArgs a = level_args(j);
+            a.cap_m = (int32_t)m;
+            a.cap_n = (int32_t)n;
+            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 28.0 : 12.0) * m + 8.0 * n,
+                     launch_min_incident(l0, a, s));
+            PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 28.0 : 24.0) * n, launch_own(l0, a, s));
+            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 21.0 * m, launch_classify(a, s));
+            for (int round = 0;; ++round) {
+                if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
+                a.round = round;
+                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 24.0 : 16.0) * n, launch_jump(a, s));
+                ++st.jump_launches;
+                rc = read_ctrl(ctrl, hctrl, s);
+                if (rc != PANDORA_OK) return rc;
+                if (hctrl->err) return status_from_err(hctrl->err);
+                if (!(hctrl->not_converged & (1u << (round & 31)))) break;
+            }
+            const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
+            if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
+                return PANDORA_ERR_NOT_A_TREE;
+            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 40.0 * m_next, launch_compact(a, s));
+            n = n_next;
+            m = m_next;
+            ++j;
         }
-        const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
-        if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
-            return PANDORA_ERR_NOT_A_TREE;
-        PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 40.0 * m_next, launch_compact(a, s));
-        st.sum_edges += m;
-        ++st.levels;
-        off += n;
-        n = n_next;
-        m = m_next;
-        E = out;
-        ++j;
+    } else {
+        // Sync-free: every level that could exceed the LDS tail is launched with
+        // capacity-sized grids; levels that turn out small or empty return at
+        // once.  Nothing is read back until the end, so the whole call can be
+        // captured in a graph.
+        for (int j = 0; j < L.Lmax && !tail_level(L.capE[j], L.capV[j], kTailE, kTailV); ++j) {
+            const bool l0 = j == 0;
+            LevelArgs a = level_args(j);
+            const double mj = (double)L.capE[j], nj = (double)L.capV[j];
+            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, 12.0 * mj, launch_min_incident(l0, a, s));
+            PD_TIMED(l0 ? PK_OWN : PK_OWN_N, 24.0 * nj, launch_own(l0, a, s));
+            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 21.0 * mj, launch_classify(a, s));
+            for (int round = 0; round < kSyncFreeJumpRounds; ++round) {
+                a.round = round;
+                a.jump_steps = round + 1 < kSyncFreeJumpRounds ? jump_steps : (int)std::max<int64_t>(L.capV[j], 16);
+                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, 24.0 * nj, launch_jump(a, s));
+                ++st.jump_launches;
+            }
+            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 14.0 * mj, launch_compact(a, s));
+        }
     }
 
     // ---- 3. remaining levels in LDS -------------------------------------------------
     {
         TailArgs t{};
-        t.m = (int32_t)m;
-        t.n = (int32_t)n;
-        t.E = E;
+        t.EA = EA;
+        t.EB = EB;
         t.in_u = u;
         t.in_v = v;
         t.rank = rank;
-        t.level0 = j == 0 ? 1 : 0;
-        t.off = off;
         t.flat_cap = L.flat_cap;
         t.vinfo_all = vinfo_all;
         t.svflat = svflat;
@@ -446,9 +487,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         t.vertex_parent = vertex_parent;
         t.forest = forest;
         t.ctrl = ctrl;
-        st.tail_entry_edges = m;
-        st.sum_edges += m;
-        PD_TIMED(PK_TAIL, 16.0 * m, launch_tail(t, s));
+        PD_TIMED(PK_TAIL, 16.0 * kTailE, launch_tail(t, s));
     }
 
     // ---- 4. expansion -----------------------------------------------------------------
@@ -499,14 +538,56 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
         sa.forest = forest;
         PD_TIMED(PK_STITCH, 12.0 * M, launch_stitch(sa, s));
     }
-    rc = read_ctrl(ws, ctrl, hctrl, s);
+    return PANDORA_OK;
+}
+
+// Waits for the enqueued call, reads its control block back and checks it.
+int finish(const Scratch& sc, const Layout& L, int32_t B, hipStream_t s, Stats& st) {
+    Control* ctrl = at<Control>(sc.dev, L.ctrl);
+    Control* hctrl = static_cast<Control*>(sc.host);
+    const int rc = read_ctrl(ctrl, hctrl, s, kCtrlLevelsReadback);
     if (rc != PANDORA_OK) return rc;
     if (hctrl->err) return status_from_err(hctrl->err);
     if ((int64_t)hctrl->isolated != B) return PANDORA_ERR_NOT_A_TREE;
+    int entry = 0;
+    while (entry + 1 < kMaxLevels && !tail_level(hctrl->lv[entry].m, hctrl->lv[entry].n, kTailE, kTailV)) {
+        st.sum_edges += hctrl->lv[entry].m;
+        ++entry;
+    }
+    st.tail_entry_edges = hctrl->lv[entry].m;
+    st.sum_edges += hctrl->lv[entry].m;
     st.tail_levels = hctrl->tail_levels;
-    st.levels += hctrl->tail_levels;
-    g_last = st;
+    st.levels = entry + hctrl->tail_levels;
     return PANDORA_OK;
+}
+
+// The whole path for a forest described by host offsets voff[0..B].
+int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, const float* w,
+        int32_t* edge_parent, int32_t* vertex_parent, hipStream_t s) {
+    const int64_t N = voff[B];
+    const int64_t M = N - B;
+    Stats st;
+    if (M == 0) {   // only single-vertex trees: every vertex is a root
+        PD_TRY(launch_fill_i32(vertex_parent, N, -1, s));
+        PD_TRY(hipStreamSynchronize(s));
+        g_last = st;
+        return PANDORA_OK;
+    }
+    int dev = 0;
+    PD_TRY(hipGetDevice(&dev));
+    Workspace& ws = *workspace_for(dev, s);
+    std::lock_guard<std::mutex> lock(ws.mu);
+    const pandora_tuning_t tune = current_tuning();
+    const Layout L = make_layout(N, B, tune.chain_digit_bits);
+    int rc = ensure(ws, L.total, host_bytes_for(B));
+    if (rc != PANDORA_OK) return rc;
+    const Scratch sc{ws.dev, ws.host};
+    rc = enqueue(sc, L, tune, M <= (int64_t)tune.sync_free_max_edges, voff, B, u, v, w, edge_parent,
+                 vertex_parent, s, st);
+    if (rc != PANDORA_OK) return rc;
+    rc = finish(sc, L, B, s, st);
+    if (rc == PANDORA_OK) g_last = st;
+    return rc;
 }
 
 int run_and_drain(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, const float* w,
@@ -552,11 +633,27 @@ size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B) {
 }
 
 int pandora_last_stats(int64_t* out, int cap) {
-    const int64_t vals[5] = {g_last.levels, g_last.sum_edges, g_last.jump_launches, g_last.tail_levels,
-                             g_last.tail_entry_edges};
+    const int64_t vals[6] = {g_last.levels, g_last.sum_edges, g_last.jump_launches, g_last.tail_levels,
+                             g_last.tail_entry_edges, g_last.sync_free};
     int k = 0;
-    for (; k < cap && k < 5; ++k) out[k] = vals[k];
+    for (; k < cap && k < 6; ++k) out[k] = vals[k];
     return k;
+}
+
+int pandora_set_tuning(const pandora_tuning_t* t) {
+    if (!t) return PANDORA_ERR_INVALID_ARG;
+    if (t->sync_free_max_edges < 0 || t->jump_steps < 1 || t->jump_steps > 4096 ||
+        !(t->chain_digit_bits == 0 || t->chain_digit_bits == 8 || t->chain_digit_bits == 9))
+        return PANDORA_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune = *t;
+    return PANDORA_OK;
+}
+
+int pandora_get_tuning(pandora_tuning_t* t) {
+    if (!t) return PANDORA_ERR_INVALID_ARG;
+    *t = current_tuning();
+    return PANDORA_OK;
 }
 
 int pandora_profile_enable(uint32_t kind_mask) {
@@ -584,6 +681,120 @@ int pandora_profile_read(double* ms, double* bytes, int64_t* launches, int cap) 
 const char* pandora_profile_name(int kind) {
     return (kind >= 0 && kind < PK_COUNT) ? kProfNames[kind] : "";
 }
+
+struct pandora_graph {
+    Layout L;
+    int32_t B = 0;
+    int64_t M = 0;
+    void* dev = nullptr;
+    void* host = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void graph_free(pandora_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->dev) (void)hipFree(g->dev);
+    if (g->host) (void)hipHostFree(g->host);
+    delete g;
+}
+
+static int graph_create(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
+                        const float* w, int32_t* edge_parent, int32_t* vertex_parent,
+                        pandora_graph** out) {
+    *out = nullptr;
+    const int64_t N = voff[B];
+    const int64_t M = N - B;
+    pandora_graph* g = new pandora_graph;
+    g->B = B;
+    g->M = M;
+    const pandora_tuning_t tune = current_tuning();
+    if (M > 0) {
+        g->L = make_layout(N, B, tune.chain_digit_bits);
+        if (hipMalloc(&g->dev, g->L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            g->dev = nullptr;
+            graph_free(g);
+            return PANDORA_ERR_OUT_OF_MEMORY;
+        }
+    }
+    if (hipHostMalloc(&g->host, host_bytes_for(B), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        g->host = nullptr;
+        graph_free(g);
+        return PANDORA_ERR_OUT_OF_MEMORY;
+    }
+    // Capture on a private stream: the legacy default stream cannot be captured.
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        graph_free(g);
+        return PANDORA_ERR_HIP;
+    }
+    int rc = PANDORA_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = PANDORA_ERR_HIP;
+    } else {
+        t_capturing = true;
+        Stats st;
+        if (M == 0) {
+            if (launch_fill_i32(vertex_parent, N, -1, cs) != hipSuccess) rc = PANDORA_ERR_HIP;
+        } else {
+            const Scratch sc{g->dev, g->host};
+            rc = enqueue(sc, g->L, tune, true, voff, B, u, v, w, edge_parent, vertex_parent, cs, st);
+        }
+        t_capturing = false;
+        if (hipStreamEndCapture(cs, &g->graph) != hipSuccess && rc == PANDORA_OK) rc = PANDORA_ERR_HIP;
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc == PANDORA_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = PANDORA_ERR_HIP;
+    if (rc != PANDORA_OK) {
+        (void)hipGetLastError();
+        graph_free(g);
+        return rc;
+    }
+    *out = g;
+    return PANDORA_OK;
+}
+
+int pandora_graph_create(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                         int32_t* edge_parent, int32_t* vertex_parent, pandora_graph_t** out) {
+    if (!out) return PANDORA_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n < 1 || n > INT32_MAX || !vertex_parent) return PANDORA_ERR_INVALID_ARG;
+    if (n > 1 && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    const int64_t voff[2] = {0, n};
+    return graph_create(1, voff, u, v, w, edge_parent, vertex_parent, out);
+}
+
+int pandora_graph_create_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
+                                 const float* w, int32_t* edge_parent, int32_t* vertex_parent,
+                                 pandora_graph_t** out) {
+    if (!out) return PANDORA_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (B < 1 || !voff || !vertex_parent || voff[0] != 0) return PANDORA_ERR_INVALID_ARG;
+    for (int32_t b = 0; b < B; ++b)
+        if (voff[b + 1] <= voff[b]) return PANDORA_ERR_INVALID_ARG;
+    if (voff[B] > INT32_MAX) return PANDORA_ERR_INVALID_ARG;
+    if (voff[B] > B && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    return graph_create(B, voff, u, v, w, edge_parent, vertex_parent, out);
+}
+
+int pandora_graph_launch(pandora_graph_t* g, void* hip_stream) {
+    if (!g || !g->exec) return PANDORA_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (hipGraphLaunch(g->exec, s) != hipSuccess) return PANDORA_ERR_HIP;
+    if (g->M == 0) return hipStreamSynchronize(s) == hipSuccess ? PANDORA_OK : PANDORA_ERR_HIP;
+    Stats st;
+    st.sync_free = 1;
+    const int rc = finish(Scratch{g->dev, g->host}, g->L, g->B, s, st);
+    if (rc == PANDORA_OK) g_last = st;
+    return rc;
+}
+
+void pandora_graph_destroy(pandora_graph_t* g) { graph_free(g); }
 
 void pandora_release_workspaces(void) {
     std::lock_guard<std::mutex> g(g_mu);
