@@ -102,15 +102,21 @@ int pandora_last_stats(int64_t* out, int cap);
  *   jump_steps           pointer-jumping steps per thread per launch [16]
  *   chain_digit_bits     radix digit width of the chain sort: 8, 9, or 0 for
  *                        8 [0]
- * pandora_set_tuning returns INVALID_ARG for out-of-range values. */
+ *   sort_tile_cfg        radix tile: 0..3 = 1024, 2048, 4096, 8192 keys per
+ *                        workgroup [3]
+ * pandora_set_tuning returns INVALID_ARG for out-of-range values.
+ * pandora_set_thread_tuning overrides them for calls made by the calling
+ * thread only (NULL removes the override), so concurrent callers can tune
+ * per call size without affecting each other. */
 typedef struct {
     int32_t sync_free_max_edges;
     int32_t jump_steps;
     int32_t chain_digit_bits;
-    int32_t reserved;
+    int32_t sort_tile_cfg;
 } pandora_tuning_t;
 int pandora_set_tuning(const pandora_tuning_t* t);
 int pandora_get_tuning(pandora_tuning_t* t);
+int pandora_set_thread_tuning(const pandora_tuning_t* t);
 
 /* Per-kernel profiler (tracing).  pandora_profile_enable(mask) clears the
  * counters and, for every kernel kind k with bit k set in mask, brackets each

@@ -42,10 +42,10 @@ _lib = None
 class Tuning(ctypes.Structure):
     """Mirror of pandora_tuning_t (speed knobs only; results never change)."""
     _fields_ = [("sync_free_max_edges", ctypes.c_int32), ("jump_steps", ctypes.c_int32),
-                ("chain_digit_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("chain_digit_bits", ctypes.c_int32), ("sort_tile_cfg", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 def _load():
@@ -75,6 +75,8 @@ def _load():
     lib.pandora_profile_name.restype = ctypes.c_char_p
     lib.pandora_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.pandora_set_tuning.restype = ctypes.c_int
+    lib.pandora_set_thread_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.pandora_set_thread_tuning.restype = ctypes.c_int
     lib.pandora_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.pandora_get_tuning.restype = ctypes.c_int
     lib.pandora_graph_create.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_void_p)]
@@ -126,8 +128,36 @@ def _as_dev(t, dtype, device):
     return t.contiguous()
 
 
+# Per-call tuning: a function edges -> tuning dict (or None), installed by
+# autotune.install.  By default the table shipped for this GPU architecture is
+# used when there is one (set PANDORA_AUTOTUNE=0 to disable).
+_tuning_hook = None
+_tuning_checked = False
+
+
+def _set_tuning_hook(fn) -> None:
+    global _tuning_hook, _tuning_checked
+    _tuning_hook = fn
+    _tuning_checked = True
+
+
+def _apply_tuning(edges: int) -> None:
+    global _tuning_checked
+    if not _tuning_checked:
+        _tuning_checked = True
+        if os.environ.get("PANDORA_AUTOTUNE", "1") != "0":
+            from . import autotune
+            table = autotune.load()
+            if table is not None:
+                autotune.install(table)
+    if _tuning_hook is not None:
+        t = _tuning_hook(int(edges))
+        set_thread_tuning(t)
+
+
 def dendrogram_into(n: int, u, v, w, edge_parent, vertex_parent, stream=None) -> int:
     """Raw call: writes into preallocated int32 device tensors; returns the status."""
+    _apply_tuning(int(n) - 1)
     return _load().pandora_dendrogram(int(n), _dptr(u), _dptr(v), _dptr(w), _dptr(edge_parent),
                                       _dptr(vertex_parent), _stream_handle(stream))
 
@@ -175,6 +205,7 @@ def dendrogram_batched(voff, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
     with torch.cuda.device(dev):
         ep = torch.empty(M, dtype=torch.int32, device=dev)
         vp = torch.empty(N, dtype=torch.int32, device=dev)
+        _apply_tuning(M)
         st = _load().pandora_dendrogram_batched(
             B, ctypes.c_void_p(voff_t.data_ptr()), _dptr(u), _dptr(v), _dptr(w), _dptr(ep), _dptr(vp),
             _stream_handle(stream))
@@ -205,6 +236,14 @@ def set_tuning(**kw) -> dict:
     t = Tuning(**{**old, **kw})
     _check(_load().pandora_set_tuning(ctypes.byref(t)))
     return old
+
+
+def set_thread_tuning(tuning: Optional[dict]) -> None:
+    """Tuning for calls made by this thread only (None: use the process-wide one)."""
+    if tuning is None:
+        _check(_load().pandora_set_thread_tuning(None))
+    else:
+        _check(_load().pandora_set_thread_tuning(ctypes.byref(Tuning(**tuning))))
 
 
 def release_workspaces():
@@ -250,6 +289,7 @@ class Graph:
         self.v = _as_dev(v, torch.int32, dev)
         self.w = _as_dev(w, torch.float32, dev)
         m = w.numel()
+        _apply_tuning(m)
         with torch.cuda.device(dev):
             if voff is None:
                 n = m + 1 if n is None else int(n)

@@ -9,23 +9,28 @@
 namespace pandora {
 
 // ---- radix sort (stable LSD, 8-bit digits, one-sweep chained scan) ----------
-#ifndef PANDORA_SORT_BLOCK
-#define PANDORA_SORT_BLOCK 512
-#endif
-#ifndef PANDORA_SORT_ITEMS
-#define PANDORA_SORT_ITEMS 16
-#endif
 constexpr int kMaxRadixBits = 9;                      // digits of 8 or 9 bits
 constexpr int kMaxRadix = 1 << kMaxRadixBits;
-constexpr int kSortBlock = PANDORA_SORT_BLOCK;
-constexpr int kSortItems = PANDORA_SORT_ITEMS;
-constexpr int kSortTile = kSortBlock * kSortItems;   // keys per workgroup
+
+// Radix tile configurations (threads x keys per thread), chosen at run time:
+// small inputs want small tiles (more workgroups), large ones long digit
+// runs per tile (contiguous scatters).  9-bit digits need 512 threads (one
+// per digit), so they use 512 threads at the same tile size.
+constexpr int kNumSortCfg = 4;
+constexpr int kDefaultSortCfg = 3;
+__host__ __device__ constexpr int sort_cfg_tile(int cfg) {
+    return cfg == 0 ? 1024 : cfg == 1 ? 2048 : cfg == 2 ? 4096 : 8192;
+}
+__host__ __device__ constexpr int sort_cfg_block(int cfg, int bits) {
+    return bits == 9 ? 512 : (cfg == 3 ? 512 : 256);
+}
 
 enum SortSrc { SRC_WEIGHT = 0, SRC_KEYS = 1 };
 enum SortDst { DST_KEYS = 0, DST_RANK = 1 };
 
 struct SortPassArgs {
     int64_t n;
+    int cfg;                   // tile configuration (sort_cfg_tile / sort_cfg_block)
     int bits;                  // digit width of this pass: 8 or 9
     int shift;                 // bit offset of this pass's digit
     int pass;                  // row of Control::hist / sort_tiles
@@ -60,7 +65,9 @@ struct SortHistArgs {
 hipError_t launch_sort_hist(int src, const SortHistArgs& a, hipStream_t s);
 hipError_t launch_sort_pass(int src, int dst, const SortPassArgs& a, hipStream_t s);
 
-__host__ __device__ inline int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+__host__ __device__ inline int64_t sort_tiles(int64_t n, int cfg) {
+    return (n + sort_cfg_tile(cfg) - 1) / sort_cfg_tile(cfg);
+}
 
 // ---- contraction levels -------------------------------------------------------
 constexpr int kScanBlock = 256;

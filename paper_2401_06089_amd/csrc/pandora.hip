@@ -42,12 +42,22 @@ pandora_tuning_t g_tune = {
     /*sync_free_max_edges=*/0,
     /*jump_steps=*/16,
     /*chain_digit_bits=*/0,
-    /*reserved=*/0,
+    /*sort_tile_cfg=*/kDefaultSortCfg,
 };
 
+thread_local bool t_has_tune = false;
+thread_local pandora_tuning_t t_tune;
+
 pandora_tuning_t current_tuning() {
+    if (t_has_tune) return t_tune;
     std::lock_guard<std::mutex> g(g_tune_mu);
     return g_tune;
+}
+
+bool tuning_valid(const pandora_tuning_t* t) {
+    return t->sync_free_max_edges >= 0 && t->jump_steps >= 1 && t->jump_steps <= 4096 &&
+           (t->chain_digit_bits == 0 || t->chain_digit_bits == 8 || t->chain_digit_bits == 9) &&
+           t->sort_tile_cfg >= 0 && t->sort_tile_cfg < kNumSortCfg;
 }
 
 struct Layout {
@@ -58,6 +68,8 @@ struct Layout {
     int64_t flat_cap = 0;
     int chain_passes = 0;
     int chain_bits = 8;
+    int sort_cfg = kDefaultSortCfg;
+    int64_t lb_words_w = 0, lb_words_c = 0;   // look-back words per pass (weight / chain sort)
     size_t ctrl, voff, K0, K1, V0, V1, perm, rank, E0, EA, EB, min64, own, alpha, scan_lb,
         tile_excl, vinfo, ptr, svflat, lb0, lb1;
     size_t total = 0;
@@ -75,7 +87,7 @@ int ceil_log2(int64_t x) {   // smallest L with 2^L >= x (x >= 1)
     return L;
 }
 
-Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0) {
+Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg = kDefaultSortCfg) {
     Layout L;
     L.N = N;
     L.B = B;
@@ -108,7 +120,10 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0) {
     }
 
     const int64_t E1 = std::max<int64_t>(L.capE[1], 1), E2 = std::max<int64_t>(L.capE[2], 1);
-    const int64_t sortlb = sort_tiles(std::max<int64_t>(M, 1)) * kMaxRadix;
+    L.sort_cfg = sort_cfg;
+    L.lb_words_w = sort_tiles(std::max<int64_t>(M, 1), sort_cfg) * 256;
+    L.lb_words_c = sort_tiles(std::max<int64_t>(M, 1), sort_cfg) * (int64_t(1) << L.chain_bits);
+    const int64_t sortlb = std::max(L.lb_words_w, L.lb_words_c);
     const int64_t scant = scan_tiles(std::max<int64_t>(M, 1));
     size_t c = 0;
     L.ctrl = take(c, sizeof(Control));
@@ -337,7 +352,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
     int32_t* perm = at<int32_t>(d, L.perm);
     VInfo* vinfo_all = at<VInfo>(d, L.vinfo);
     int32_t* svflat = at<int32_t>(d, L.svflat);
-    const int64_t lb_words = sort_tiles(M) * kMaxRadix;
+    const int64_t lb_words = L.lb_words_w;
 
     PD_TIMED(PK_ZERO, sizeof(Control), launch_zero_control(ctrl, (int32_t)M, (int32_t)N, s));
 
@@ -365,6 +380,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         for (int p = 0; p < 4; ++p) {
             SortPassArgs a{};
             a.n = M;
+            a.cfg = L.sort_cfg;
             a.bits = 8;
             a.shift = 8 * p;
             a.pass = p;
@@ -503,7 +519,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         wa.hist_row = 4;
         wa.passes = L.chain_passes;
         wa.lb_zero = LB[0];
-        wa.lb_zero_words = lb_words;
+        wa.lb_zero_words = L.lb_words_c;
         wa.ctrl = ctrl;
         PD_TIMED(PK_WALK_HIST, 12.0 * M, launch_walk_hist(wa, s));
         const uint32_t* kin = K[0];
@@ -511,6 +527,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         for (int p = 0; p < L.chain_passes; ++p) {
             SortPassArgs a{};
             a.n = M;
+            a.cfg = L.sort_cfg;
             a.bits = L.chain_bits;
             a.shift = L.chain_bits * p;
             a.pass = 4 + p;
@@ -520,7 +537,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             a.vals_out = V[(p + 1) & 1];
             a.lb = LB[p & 1];
             a.lb_zero = LB[(p + 1) & 1];
-            a.lb_zero_words = lb_words;
+            a.lb_zero_words = L.lb_words_c;
             a.ctrl = ctrl;
             PD_TIMED(PK_SORT_C_PASS, 16.0 * M, launch_sort_pass(SRC_KEYS, DST_KEYS, a, s));
             kin = K[(p + 1) & 1];
@@ -578,7 +595,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     Workspace& ws = *workspace_for(dev, s);
     std::lock_guard<std::mutex> lock(ws.mu);
     const pandora_tuning_t tune = current_tuning();
-    const Layout L = make_layout(N, B, tune.chain_digit_bits);
+    const Layout L = make_layout(N, B, tune.chain_digit_bits, tune.sort_tile_cfg);
     int rc = ensure(ws, L.total, host_bytes_for(B));
     if (rc != PANDORA_OK) return rc;
     const Scratch sc{ws.dev, ws.host};
@@ -641,12 +658,20 @@ int pandora_last_stats(int64_t* out, int cap) {
 }
 
 int pandora_set_tuning(const pandora_tuning_t* t) {
-    if (!t) return PANDORA_ERR_INVALID_ARG;
-    if (t->sync_free_max_edges < 0 || t->jump_steps < 1 || t->jump_steps > 4096 ||
-        !(t->chain_digit_bits == 0 || t->chain_digit_bits == 8 || t->chain_digit_bits == 9))
-        return PANDORA_ERR_INVALID_ARG;
+    if (!t || !tuning_valid(t)) return PANDORA_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = *t;
+    return PANDORA_OK;
+}
+
+int pandora_set_thread_tuning(const pandora_tuning_t* t) {
+    if (!t) {
+        t_has_tune = false;
+        return PANDORA_OK;
+    }
+    if (!tuning_valid(t)) return PANDORA_ERR_INVALID_ARG;
+    t_tune = *t;
+    t_has_tune = true;
     return PANDORA_OK;
 }
 
@@ -712,7 +737,7 @@ static int graph_create(int32_t B, const int64_t* voff, const int32_t* u, const 
     g->M = M;
     const pandora_tuning_t tune = current_tuning();
     if (M > 0) {
-        g->L = make_layout(N, B, tune.chain_digit_bits);
+        g->L = make_layout(N, B, tune.chain_digit_bits, tune.sort_tile_cfg);
         if (hipMalloc(&g->dev, g->L.total) != hipSuccess) {
             (void)hipGetLastError();
             g->dev = nullptr;

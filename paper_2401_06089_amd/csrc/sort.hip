@@ -29,7 +29,6 @@ constexpr uint64_t kFlagMask = 3ull << 62;
 constexpr uint64_t kCountMask = ~kFlagMask;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-static_assert(kSortBlock >= kMaxRadix, "threads below the radix own one digit each");
 
 // Exclusive scan of one value per thread across a block of BLOCK threads.
 template <int BLOCK>
@@ -79,9 +78,11 @@ __global__ __launch_bounds__(256) void k_sort_hist(SortHistArgs a) {
     }
 }
 
-template <int BITS, int SRC, int DST>
+template <int BITS, int SRC, int DST, int kSortBlock, int kSortItems>
 __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
     constexpr int kRadix = 1 << BITS;
+    constexpr int kSortTile = kSortBlock * kSortItems;
+    static_assert(kSortBlock >= kRadix, "threads below the radix own one digit each");
     constexpr int W = kSortBlock / kWave;
     __shared__ uint32_t s_cnt[W][kRadix];     // per-wave digit counters, then offsets
     __shared__ uint32_t s_start[kRadix];      // first local slot of each digit
@@ -244,20 +245,34 @@ hipError_t launch_sort_hist(int src, const SortHistArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int BITS>
-void launch_pass_bits(int src, int dst, const SortPassArgs& a, dim3 grid, dim3 block, hipStream_t s) {
-    if (src == SRC_WEIGHT && dst == DST_KEYS) k_sort_pass<BITS, SRC_WEIGHT, DST_KEYS><<<grid, block, 0, s>>>(a);
-    else if (src == SRC_WEIGHT) k_sort_pass<BITS, SRC_WEIGHT, DST_RANK><<<grid, block, 0, s>>>(a);
-    else if (dst == DST_KEYS) k_sort_pass<BITS, SRC_KEYS, DST_KEYS><<<grid, block, 0, s>>>(a);
-    else k_sort_pass<BITS, SRC_KEYS, DST_RANK><<<grid, block, 0, s>>>(a);
+template <int BITS, int BLOCK, int ITEMS>
+void launch_pass_cfg(int src, int dst, const SortPassArgs& a, dim3 grid, hipStream_t s) {
+    const dim3 block(BLOCK);
+    if (src == SRC_WEIGHT && dst == DST_KEYS) k_sort_pass<BITS, SRC_WEIGHT, DST_KEYS, BLOCK, ITEMS><<<grid, block, 0, s>>>(a);
+    else if (src == SRC_WEIGHT) k_sort_pass<BITS, SRC_WEIGHT, DST_RANK, BLOCK, ITEMS><<<grid, block, 0, s>>>(a);
+    else if (dst == DST_KEYS) k_sort_pass<BITS, SRC_KEYS, DST_KEYS, BLOCK, ITEMS><<<grid, block, 0, s>>>(a);
+    else k_sort_pass<BITS, SRC_KEYS, DST_RANK, BLOCK, ITEMS><<<grid, block, 0, s>>>(a);
 }
 
 hipError_t launch_sort_pass(int src, int dst, const SortPassArgs& a, hipStream_t s) {
-    const int64_t tiles = sort_tiles(a.n);
+    const int64_t tiles = sort_tiles(a.n, a.cfg);
     if (tiles < 1) return hipSuccess;
-    const dim3 grid((unsigned)tiles), block(kSortBlock);
-    if (a.bits == 9) launch_pass_bits<9>(src, dst, a, grid, block, s);
-    else launch_pass_bits<8>(src, dst, a, grid, block, s);
+    const dim3 grid((unsigned)tiles);
+    if (a.bits == 9) {
+        switch (a.cfg) {
+            case 0: launch_pass_cfg<9, 512, 2>(src, dst, a, grid, s); break;
+            case 1: launch_pass_cfg<9, 512, 4>(src, dst, a, grid, s); break;
+            case 2: launch_pass_cfg<9, 512, 8>(src, dst, a, grid, s); break;
+            default: launch_pass_cfg<9, 512, 16>(src, dst, a, grid, s); break;
+        }
+    } else {
+        switch (a.cfg) {
+            case 0: launch_pass_cfg<8, 256, 4>(src, dst, a, grid, s); break;
+            case 1: launch_pass_cfg<8, 256, 8>(src, dst, a, grid, s); break;
+            case 2: launch_pass_cfg<8, 256, 16>(src, dst, a, grid, s); break;
+            default: launch_pass_cfg<8, 512, 16>(src, dst, a, grid, s); break;
+        }
+    }
     return hipGetLastError();
 }
 
