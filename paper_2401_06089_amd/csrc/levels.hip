@@ -144,6 +144,10 @@ __global__ __launch_bounds__(256) void k_own(LevelArgs a) {
     }
 }
 
+// Level 0 and the deeper levels get separate instantiations of the remaining
+// kernels too, so that per-kernel profiles separate the two (their sizes
+// differ by the contraction factor).
+template <bool L0>
 __global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
     constexpr int W = kScanBlock / kWave;
     __shared__ uint32_t s_ca[kScanItems][W];
@@ -260,6 +264,7 @@ __global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
     }
 }
 
+template <bool L0>
 __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
     const LevelView L = level_view(a);
     if (L.skip) return;
@@ -302,6 +307,7 @@ __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
     a.svflat[r] = flat;                          // the lightest edge of x falls into this supervertex
 }
 
+template <bool L0>
 __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
     constexpr int W = kScanBlock / kWave;
     __shared__ uint32_t s_ca[kScanItems][W];
@@ -598,17 +604,20 @@ hipError_t launch_own(bool level0, const LevelArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_classify(const LevelArgs& a, hipStream_t s) {
-    k_classify<<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
+    if (a.level == 0) k_classify<true><<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
+    else k_classify<false><<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_jump(const LevelArgs& a, hipStream_t s) {
-    k_jump<<<blocks_for(a.cap_n, 256), 256, 0, s>>>(a);
+    if (a.level == 0) k_jump<true><<<blocks_for(a.cap_n, 256), 256, 0, s>>>(a);
+    else k_jump<false><<<blocks_for(a.cap_n, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_compact(const LevelArgs& a, hipStream_t s) {
-    k_compact<<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
+    if (a.level == 0) k_compact<true><<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
+    else k_compact<false><<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
