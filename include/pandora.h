@@ -43,6 +43,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+/* Only the functions below are exported from libpandora.so. */
+#define PANDORA_API __attribute__((visibility("default")))
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -67,7 +70,7 @@ typedef enum {
  *   hip_stream     hipStream_t to enqueue on, or NULL
  * For n == 1 the edge arrays may be NULL.
  */
-int pandora_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+PANDORA_API int pandora_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const float* w,
                        int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream);
 
 /*
@@ -79,20 +82,21 @@ int pandora_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const floa
  * the tree's first edge.  Each tree's result is identical to what
  * pandora_dendrogram returns for it alone.
  */
-int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
+PANDORA_API int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
                                const float* w, int32_t* edge_parent, int32_t* vertex_parent,
                                void* hip_stream);
 
 /* Device scratch bytes a call with n_total_vertices over B trees needs
  * (admission control and preallocation).  0 on invalid sizes. */
-size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B);
+PANDORA_API size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B);
 
 /* Per-stage statistics of the last successful call on this thread:
  * out[0] = levels, out[1] = sum of edges over all levels, out[2] = pointer
  * jumping launches, out[3] = levels done in the LDS tail, out[4] = edges at
  * the level the LDS tail started from, out[5] = 1 if the call ran without
- * host round trips.  Returns the number filled (<= cap). */
-int pandora_last_stats(int64_t* out, int cap);
+ * host round trips.  Returns the number filled (<= cap), or
+ * -PANDORA_ERR_INVALID_ARG for a NULL out or a negative cap. */
+PANDORA_API int pandora_last_stats(int64_t* out, int cap);
 
 /* Process-wide tuning knobs (defaults in brackets), read at the start of
  * every call.  They change speed only, never results.
@@ -114,9 +118,9 @@ typedef struct {
     int32_t chain_digit_bits;
     int32_t sort_tile_cfg;
 } pandora_tuning_t;
-int pandora_set_tuning(const pandora_tuning_t* t);
-int pandora_get_tuning(pandora_tuning_t* t);
-int pandora_set_thread_tuning(const pandora_tuning_t* t);
+PANDORA_API int pandora_set_tuning(const pandora_tuning_t* t);
+PANDORA_API int pandora_get_tuning(pandora_tuning_t* t);
+PANDORA_API int pandora_set_thread_tuning(const pandora_tuning_t* t);
 
 /* Per-kernel profiler (tracing).  pandora_profile_enable(mask) clears the
  * counters and, for every kernel kind k with bit k set in mask, brackets each
@@ -125,9 +129,9 @@ int pandora_set_thread_tuning(const pandora_tuning_t* t);
  * the summed algorithmic bytes (the minimum traffic of each launch) and the
  * launch count; it returns the number of kinds (<= cap).  Kind names come
  * from pandora_profile_name.  Counters are process-wide. */
-int pandora_profile_enable(uint32_t kind_mask);
-int pandora_profile_read(double* ms, double* bytes, int64_t* launches, int cap);
-const char* pandora_profile_name(int kind);
+PANDORA_API int pandora_profile_enable(uint32_t kind_mask);
+PANDORA_API int pandora_profile_read(double* ms, double* bytes, int64_t* launches, int cap);
+PANDORA_API const char* pandora_profile_name(int kind);
 
 /* Captured calls (HIP graphs).  pandora_graph_create captures the whole
  * method for fixed arguments -- the same pointers and sizes as
@@ -140,19 +144,19 @@ const char* pandora_profile_name(int kind);
  * copied at creation).  pandora_graph_destroy frees the graph and its
  * memory. */
 typedef struct pandora_graph pandora_graph_t;
-int pandora_graph_create(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+PANDORA_API int pandora_graph_create(int64_t n, const int32_t* u, const int32_t* v, const float* w,
                          int32_t* edge_parent, int32_t* vertex_parent, pandora_graph_t** out);
-int pandora_graph_create_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
+PANDORA_API int pandora_graph_create_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
                                  const float* w, int32_t* edge_parent, int32_t* vertex_parent,
                                  pandora_graph_t** out);
-int pandora_graph_launch(pandora_graph_t* g, void* hip_stream);
-void pandora_graph_destroy(pandora_graph_t* g);
+PANDORA_API int pandora_graph_launch(pandora_graph_t* g, void* hip_stream);
+PANDORA_API void pandora_graph_destroy(pandora_graph_t* g);
 
 /* Free every cached scratch allocation (waits for the owning streams). */
-void pandora_release_workspaces(void);
+PANDORA_API void pandora_release_workspaces(void);
 
 /* Human-readable name of a status code (static string). */
-const char* pandora_status_string(int status);
+PANDORA_API const char* pandora_status_string(int status);
 
 #ifdef __cplusplus
 }

@@ -231,10 +231,15 @@ def get_tuning() -> dict:
 
 
 def set_tuning(**kw) -> dict:
-    """Update process-wide tuning knobs; returns the previous values."""
+    """Update process-wide tuning knobs; returns the previous values.
+
+    Explicit knobs win: this also turns off the autotuned table for the rest
+    of the process (``autotune.install`` brings a table back)."""
     old = get_tuning()
     t = Tuning(**{**old, **kw})
     _check(_load().pandora_set_tuning(ctypes.byref(t)))
+    _set_tuning_hook(None)
+    set_thread_tuning(None)
     return old
 
 

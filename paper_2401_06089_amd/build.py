@@ -22,6 +22,8 @@ HIPCC_FLAGS = [
     # packed fp32 ops stay off on these boxes (no kernel here uses fp32 math anyway)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    # only the C ABI (PANDORA_API in the header) is exported
+    "-fvisibility=hidden",
 ]
 
 

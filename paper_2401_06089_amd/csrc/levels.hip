@@ -70,6 +70,51 @@ __device__ __forceinline__ LevelView level_view(const LevelArgs& a) {
     return v;
 }
 
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)x, d, kWave);
+        const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), d, kWave);
+        x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+// Decoupled look-back by a whole wave: lane l reads the word of tile p-l, so
+// one hop covers 64 earlier tiles.  Words are consumed newest first up to the
+// nearest inclusive one, or up to the first tile that has not published yet
+// (then the wave waits there).  Every lane returns the same exclusive sum.
+__device__ uint64_t wave_lookback(const uint64_t* lb, int64_t tile, Control* ctrl) {
+    const int lane = lane_id();
+    int64_t p = tile - 1;
+    uint64_t excl = 0;
+    uint32_t spins = 0;
+    while (true) {
+        const int64_t q = p - lane;
+        const uint64_t wv = q >= 0 ? ld_relaxed(lb + q) : kFlagInc;
+        const uint64_t flag = wv & kFlagMask;
+        const uint64_t notready = ballot(flag == 0);
+        const int nr = notready ? __ffsll((long long)notready) - 1 : kWave;
+        const uint64_t usable = nr == kWave ? ~0ull : ((1ull << nr) - 1ull);
+        const uint64_t inc = ballot(flag == kFlagInc) & usable;
+        if (inc) {
+            const int f = __ffsll((long long)inc) - 1;
+            return excl + wave_sum64(lane <= f ? (wv & kCountMask) : 0ull);
+        }
+        if (nr == 0) {
+            if (++spins > kSpinLimit) {
+                if (lane == 0) raise_err(ctrl, kErrSpin);
+                return excl;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        spins = 0;
+        excl += wave_sum64(lane < nr ? (wv & kCountMask) : 0ull);
+        p -= nr;
+    }
+}
+
 // After an input error every level kernel returns at once: the call's outputs
 // are unspecified then, and nothing may index with the damaged tables.
 template <bool L0>
@@ -196,60 +241,44 @@ __global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
     }
     if (ballot(selfloop) != 0 && lane == 0) raise_err(a.ctrl, kErrNotTree);
     __syncthreads();
-    if (tid == 0) {
-        uint32_t sa = 0, sl = 0;
-        for (int k = 0; k < kScanItems; ++k)
-            for (int w = 0; w < W; ++w) {
-                const uint32_t ca = s_ca[k][w], cl = s_cl[k][w];
-                s_ca[k][w] = sa;
-                s_cl[k][w] = sl;
-                sa += ca;
-                sl += cl;
-            }
-        const uint64_t agg = ((uint64_t)sa << 31) | (uint64_t)sl;
-        uint64_t* my = a.scan_lb + tile;
-        st_relaxed(my, (tile == 0 ? kFlagInc : kFlagAgg) | agg);
-        uint64_t excl = 0;
-        if (tile > 0) {
-            int64_t p = tile - 1;
-            uint32_t spins = 0;
-            while (true) {
-                const uint64_t wv = ld_relaxed(a.scan_lb + p);
-                const uint64_t flag = wv & kFlagMask;
-                if (flag == 0) {
-                    if (++spins > kSpinLimit) {
-                        raise_err(a.ctrl, kErrSpin);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+    if (wave == 0) {
+        uint64_t agg = 0;
+        if (lane == 0) {
+            uint32_t sa = 0, sl = 0;
+            for (int k = 0; k < kScanItems; ++k)
+                for (int w = 0; w < W; ++w) {
+                    const uint32_t ca = s_ca[k][w], cl = s_cl[k][w];
+                    s_ca[k][w] = sa;
+                    s_cl[k][w] = sl;
+                    sa += ca;
+                    sl += cl;
                 }
-                spins = 0;
-                excl += wv & kCountMask;   // fields never carry: each sum < 2^31
-                if (flag == kFlagInc || p == 0) break;
-                --p;
-            }
-            st_relaxed(my, kFlagInc | (excl + agg));
+            agg = ((uint64_t)sa << 31) | (uint64_t)sl;
+            st_relaxed(a.scan_lb + tile, (tile == 0 ? kFlagInc : kFlagAgg) | agg);
         }
-        s_excl = excl;
-        a.tile_alpha_excl[tile] = (int32_t)(excl >> 31);
-        if (tile == scan_tiles(L.m) - 1) {
-            const uint64_t all = excl + agg;
-            int32_t mn = (int32_t)(all >> 31), nn = (int32_t)(all & kLow31);
-            a.ctrl->m_next = mn;
-            a.ctrl->n_next = nn;
-            // Section 4.2 bounds the next level; a larger one is not a tree.
-            if (mn > a.cap_next_e || nn > a.cap_next_v || mn >= L.m) {
-                raise_err(a.ctrl, kErrOverflow);
-                mn = 0;
-                nn = 0;
-            }
-            if (a.level + 1 < kMaxLevels) {
-                LevelInfo nx;
-                nx.m = mn;
-                nx.n = nn;
-                nx.off = L.off_next;
-                a.ctrl->lv[a.level + 1] = nx;
+        const uint64_t excl = tile > 0 ? wave_lookback(a.scan_lb, tile, a.ctrl) : 0;
+        if (lane == 0) {
+            if (tile > 0) st_relaxed(a.scan_lb + tile, kFlagInc | (excl + agg));
+            s_excl = excl;
+            a.tile_alpha_excl[tile] = (int32_t)(excl >> 31);
+            if (tile == scan_tiles(L.m) - 1) {
+                const uint64_t all = excl + agg;
+                int32_t mn = (int32_t)(all >> 31), nn = (int32_t)(all & kLow31);
+                a.ctrl->m_next = mn;
+                a.ctrl->n_next = nn;
+                // Section 4.2 bounds the next level; a larger one is not a tree.
+                if (mn > a.cap_next_e || nn > a.cap_next_v || mn >= L.m) {
+                    raise_err(a.ctrl, kErrOverflow);
+                    mn = 0;
+                    nn = 0;
+                }
+                if (a.level + 1 < kMaxLevels) {
+                    LevelInfo nx;
+                    nx.m = mn;
+                    nx.n = nn;
+                    nx.off = L.off_next;
+                    a.ctrl->lv[a.level + 1] = nx;
+                }
             }
         }
     }

@@ -652,6 +652,7 @@ size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B) {
 int pandora_last_stats(int64_t* out, int cap) {
     const int64_t vals[6] = {g_last.levels, g_last.sum_edges, g_last.jump_launches, g_last.tail_levels,
                              g_last.tail_entry_edges, g_last.sync_free};
+    if (!out || cap < 0) return -PANDORA_ERR_INVALID_ARG;
     int k = 0;
     for (; k < cap && k < 6; ++k) out[k] = vals[k];
     return k;

@@ -19,6 +19,8 @@
 // inverse, the rank of every edge, so that level 0 can run in input order.
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace pandora {
 
 namespace {
@@ -28,6 +30,14 @@ constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr uint64_t kFlagMask = 3ull << 62;
 constexpr uint64_t kCountMask = ~kFlagMask;
 constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kLookBatch = 4;   // earlier tiles read per look-back hop
+
+// Waves per SIMD to reserve registers for: the 8192-key, 8-bit pass needs
+// 52 KB of LDS, so three 512-thread workgroups fit on a CU if each wave keeps
+// to 80 VGPRs.
+constexpr int sort_waves_per_eu(int bits, int block, int items) {
+    return (bits == 8 && block == 512 && items == 16) ? 6 : 1;
+}
 
 
 // Exclusive scan of one value per thread across a block of BLOCK threads.
@@ -79,7 +89,7 @@ __global__ __launch_bounds__(256) void k_sort_hist(SortHistArgs a) {
 }
 
 template <int BITS, int SRC, int DST, int kSortBlock, int kSortItems>
-__global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
+__global__ __launch_bounds__(kSortBlock, sort_waves_per_eu(BITS, kSortBlock, kSortItems)) void k_sort_pass(SortPassArgs a) {
     constexpr int kRadix = 1 << BITS;
     constexpr int kSortTile = kSortBlock * kSortItems;
     static_assert(kSortBlock >= kRadix, "threads below the radix own one digit each");
@@ -87,8 +97,9 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
     __shared__ uint32_t s_cnt[W][kRadix];     // per-wave digit counters, then offsets
     __shared__ uint32_t s_start[kRadix];      // first local slot of each digit
     __shared__ int64_t s_gbase[kRadix];       // global slot of local slot 0 per digit
-    __shared__ uint32_t s_keys[kSortTile];
-    __shared__ int32_t s_vals[kSortTile];
+    using DigitT = typename std::conditional<(BITS <= 8), uint8_t, uint16_t>::type;
+    __shared__ uint32_t s_buf[kSortTile];    // keys, then values, in digit order
+    __shared__ DigitT s_dig[kSortTile];      // digit of each slot
     __shared__ uint32_t s_wsum[W];
     __shared__ uint32_t s_tile;
 
@@ -108,24 +119,19 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
     const int64_t base = tile * kSortTile;
     const int64_t wbase = base + (int64_t)wave * (kWave * kSortItems);
 
+    // Registers are what limits occupancy here: ranks and local slots are
+    // packed two per register (both < 2^16), and values are loaded only after
+    // the look-back, when the keys are about to leave.
+    static_assert(kWave * kSortItems <= 65536 && kSortTile <= 65536, "16-bit ranks and slots");
+    static_assert(kSortItems % 2 == 0, "items come in pairs");
     uint32_t key[kSortItems];
-    int32_t val[kSortItems];
-    uint32_t rank[kSortItems];
+    uint32_t rank2[kSortItems / 2];
 
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = wbase + k * kWave + lane;
         key[k] = 0xffffffffu;
-        val[k] = -1;
-        if (idx < a.n) {
-            if (SRC == SRC_WEIGHT) {
-                key[k] = weight_key(a.w[idx]);
-                val[k] = (int32_t)idx;
-            } else {
-                key[k] = a.keys_in[idx];
-                val[k] = a.vals_in[idx];
-            }
-        }
+        if (idx < a.n) key[k] = SRC == SRC_WEIGHT ? weight_key(a.w[idx]) : a.keys_in[idx];
     }
 
     // Stable in-wave ranking: lanes holding the same digit find each other with
@@ -141,13 +147,15 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
             const uint64_t mb = ballot(bit);
             peers &= bit ? mb : ~mb;
         }
-        rank[k] = 0;
+        uint32_t rk = 0;
         if (valid) {
             const uint64_t below = peers & lanemask_lt();
             const uint32_t c = s_cnt[wave][d];
-            rank[k] = c + (uint32_t)popc64(below);
+            rk = c + (uint32_t)popc64(below);
             if (below == 0) s_cnt[wave][d] = c + (uint32_t)popc64(peers);
         }
+        if (k & 1) rank2[k / 2] |= rk << 16;
+        else rank2[k / 2] = rk;
     }
     __syncthreads();
 
@@ -174,12 +182,29 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
         s_start[d] = start;
         uint64_t excl = 0;
         if (tile > 0) {
+            // Each hop reads kLookBatch earlier tiles at once (independent
+            // loads, one latency): consume them newest first up to the first
+            // inclusive word, or up to the first tile that has not published.
             int64_t p = tile - 1;
             uint32_t spins = 0;
-            while (true) {
-                const uint64_t wv = ld_relaxed(a.lb + p * kRadix + d);
-                const uint64_t flag = wv & kFlagMask;
-                if (flag == 0) {
+            bool done = false;
+            while (!done) {
+                uint64_t wv[kLookBatch];
+#pragma unroll
+                for (int j = 0; j < kLookBatch; ++j)
+                    wv[j] = (p - j >= 0) ? ld_relaxed(a.lb + (p - j) * kRadix + d) : kFlagInc;
+                int used = 0;
+#pragma unroll
+                for (int j = 0; j < kLookBatch; ++j) {
+                    if (done || used < j) continue;
+                    const uint64_t flag = wv[j] & kFlagMask;
+                    if (flag == 0) continue;
+                    excl += wv[j] & kCountMask;
+                    used = j + 1;
+                    if (flag == kFlagInc || p - j <= 0) done = true;
+                }
+                if (done) break;
+                if (used == 0) {
                     if (++spins > kSpinLimit) {
                         raise_err(a.ctrl, kErrSpin);
                         break;
@@ -188,9 +213,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
                     continue;
                 }
                 spins = 0;
-                excl += wv & kCountMask;
-                if (flag == kFlagInc || p == 0) break;
-                --p;
+                p -= used;
             }
             st_relaxed(my, kFlagInc | (excl + tot));
         }
@@ -198,35 +221,71 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(SortPassArgs a) {
     }
     __syncthreads();
 
-    // Place the tile in digit order in LDS.
+    // The tile leaves in digit order, keys first and values second, through
+    // one LDS buffer (half the LDS of staging both, so more workgroups fit on
+    // a CU); each slot's digit is kept beside it to find its global slot.
+    // Consecutive threads take consecutive LDS slots, so each digit's run
+    // lands on consecutive global slots.
+    // Recompute digits here rather than keep all of them alive across the
+    // look-back (an empty asm hides that the keys are unchanged).
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) asm volatile("" : "+v"(key[k]));
+#pragma unroll
+    for (int k = 0; k < kSortItems / 2; ++k) asm volatile("" : "+v"(rank2[k]));
+    uint32_t lp2[kSortItems / 2];
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
+        uint32_t slot = 0;
         if (wbase + k * kWave + lane < a.n) {
             const uint32_t dd = (key[k] >> a.shift) & (kRadix - 1);
-            const uint32_t lp = s_start[dd] + s_cnt[wave][dd] + rank[k];
-            s_keys[lp] = key[k];
-            s_vals[lp] = val[k];
+            const uint32_t rk = (rank2[k / 2] >> (16 * (k & 1))) & 0xffffu;
+            slot = s_start[dd] + s_cnt[wave][dd] + rk;
+            s_dig[slot] = (DigitT)dd;
+            if (DST == DST_KEYS) s_buf[slot] = key[k];
         }
+        if (k & 1) lp2[k / 2] |= slot << 16;
+        else lp2[k / 2] = slot;
+    }
+    // Values of the weight sort are the edge ids themselves, made where used.
+    int32_t val[kSortItems];
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t idx = wbase + k * kWave + lane;
+        val[k] = -1;
+        if (SRC == SRC_KEYS && idx < a.n) val[k] = a.vals_in[idx];
     }
     __syncthreads();
-
-    // Scatter: consecutive threads take consecutive LDS slots, so each digit's
-    // run lands on consecutive global slots.
     const int tile_n = (int)((a.n - base) < kSortTile ? (a.n - base) : kSortTile);
-    for (int i = tid; i < tile_n; i += kSortBlock) {
-        const uint32_t kk = s_keys[i];
-        const int64_t g = s_gbase[(kk >> a.shift) & (kRadix - 1)] + i;
-        const int32_t id = s_vals[i];
-        // Only reachable after a look-back failure (already reported): never
-        // write outside the arrays.
-        if (g < 0 || g >= a.n || (DST == DST_RANK && (id < 0 || id >= a.n))) continue;
-        if (DST == DST_KEYS) {
-            a.keys_out[g] = kk;
-            a.vals_out[g] = id;
-        } else {
-            a.vals_out[g] = id;
-            a.rank[id] = (int32_t)g;
+    // A global slot is out of range only after a look-back failure (already
+    // reported): never write outside the arrays.
+    if (DST == DST_KEYS) {
+#pragma unroll 4
+        for (int j = 0; j < kSortItems; ++j) {
+            const int i = tid + j * kSortBlock;
+            if (i < tile_n) {
+                const int64_t g = s_gbase[s_dig[i]] + i;
+                if (g >= 0 && g < a.n) a.keys_out[g] = s_buf[i];
+            }
         }
+        __syncthreads();
+    }
+    int lane_v = lane;   // recomputed below rather than kept from the loads
+    asm volatile("" : "+v"(lane_v));
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k)
+        if (wbase + k * kWave + lane_v < a.n)
+            s_buf[(lp2[k / 2] >> (16 * (k & 1))) & 0xffffu] =
+                SRC == SRC_WEIGHT ? (uint32_t)(wbase + k * kWave + lane_v) : (uint32_t)val[k];
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < kSortItems; ++j) {
+        const int i = tid + j * kSortBlock;
+        if (i >= tile_n) continue;
+        const int64_t g = s_gbase[s_dig[i]] + i;
+        if (g < 0 || g >= a.n) continue;
+        const int32_t id = (int32_t)s_buf[i];
+        a.vals_out[g] = id;
+        if (DST == DST_RANK && id >= 0 && id < a.n) a.rank[id] = (int32_t)g;
     }
 }
 
