@@ -50,7 +50,10 @@ def request_footprint(n: int) -> int:
 
 class DendrogramServer:
     def __init__(self, budget_bytes: int, streams: int = 4, max_batch_edges: int = 64 << 20,
-                 device: int = 0):
+                 device: int = 0, policy: str = "fifo"):
+        if policy not in ("fifo", "small_first"):
+            raise ValueError(f"unknown policy {policy!r}")
+        self.policy = policy
         self.peak_in_use = 0
         self.budget = int(budget_bytes)
         self.max_batch_edges = int(max_batch_edges)
@@ -89,22 +92,38 @@ class DendrogramServer:
 
     # ---- workers -----------------------------------------------------------------
     def _take_batch(self) -> Optional[List[Request]]:
-        """Under the lock: admit waiting requests in arrival order while they fit
-        the byte budget and the batch edge cap."""
+        """Under the lock: admit waiting requests while they fit the byte budget
+        and the batch edge cap.  "fifo" takes them in arrival order and stops at
+        the first that does not fit; "small_first" takes the smallest waiting
+        requests first (the oldest request always heads the batch, so none
+        waits behind an endless stream of smaller ones)."""
+        if not self.pending:
+            return None
+        if self.policy == "fifo":
+            order = list(range(len(self.pending)))
+        else:
+            rest = sorted(range(1, len(self.pending)), key=lambda i: self.pending[i].n)
+            order = [0] + rest
         batch: List[Request] = []
+        taken = []
         edges = 0
-        while self.pending:
-            r = self.pending[0]
+        for i in order:
+            r = self.pending[i]
             if batch and edges + (r.n - 1) > self.max_batch_edges:
-                break
+                if self.policy == "fifo":
+                    break
+                continue
             if self.in_use + r.footprint > self.budget:
                 break
-            self.pending.popleft()
             self.in_use += r.footprint
             self.peak_in_use = max(self.peak_in_use, self.in_use)
             r.admitted = time.perf_counter()
             batch.append(r)
+            taken.append(i)
             edges += r.n - 1
+        if taken:
+            keep = set(taken)
+            self.pending = collections.deque(r for i, r in enumerate(self.pending) if i not in keep)
         return batch or None
 
     def _worker(self, idx: int):
