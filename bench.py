@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -95,6 +96,26 @@ def committed_traffic(workload, kernel):
     return None
 
 
+def copy_bandwidth(dev) -> float:
+    """Device-to-device copy of 1 GiB on this GPU, read plus write bytes per second (GB/s)."""
+    import torch
+    n = 1 << 28
+    a = torch.empty(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbps = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -118,10 +139,10 @@ def main():
                     help="capture each call once into a HIP graph and replay it every step")
     ap.add_argument("--compare-per-tree", action="store_true",
                     help="c4: also time the same trees built one call per tree")
-    ap.add_argument("--duration", type=float, default=20.0, help="c5: seconds of arrivals")
+    ap.add_argument("--duration", type=float, default=60.0, help="c5: seconds of arrivals")
     ap.add_argument("--discard", type=float, default=5.0, help="c5: warm-up seconds not reported")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5: arrivals per second")
-    ap.add_argument("--pool", type=int, default=96, help="c5: distinct trees in the device pool")
+    ap.add_argument("--pool", type=int, default=512, help="c5: distinct trees in the device pool")
     ap.add_argument("--streams", type=int, default=4, help="c5: server worker streams")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="c5: admission budget")
     ap.add_argument("--max-batch-edges", type=int, default=64 << 20, help="c5: edge cap of one batch")
@@ -272,6 +293,7 @@ def main():
                      "algorithmic_GBps": sum(s["bytes"] for s in stages.values()) / (ms_per_step / 1000) / 1e9},
     }
     out["path_hbm"]["frac"] = out["path_hbm"]["algorithmic_GBps"] / HBM_PEAK_GBS
+    out["roofline"]["copy_GBps"] = copy_bandwidth(dev)
     tr = committed_traffic(args.workload, dominant)
     if tr:
         out["roofline"]["traffic"] = tr["bytes_per_launch"]
@@ -312,12 +334,32 @@ def main():
         import oracle
         log("timing the CPU oracle on the same inputs ...")
         t1 = time.perf_counter()
+        results = []
         for kind, obj in items:
             if kind == "tree":
-                oracle.dendrogram(obj.n, obj.u, obj.v, obj.w)
+                results.append(oracle.dendrogram(obj.n, obj.u, obj.v, obj.w))
             else:
-                oracle.dendrogram_batched(obj.voff, obj.u, obj.v, obj.w)
+                results.append(oracle.dendrogram_batched(obj.voff, obj.u, obj.v, obj.w))
         cpu_s = time.perf_counter() - t1
+        # Imbalance (the paper's Table 2): dendrogram height over log2 n, from
+        # the oracle's output; for a forest, the largest over its trees.
+        imb = []
+        for (kind, obj), (ep, vp) in zip(items, results):
+            if kind == "tree":
+                h = oracle.dendrogram_height(ep, vp)
+                imb.append({"n": obj.n, "height": h, "imb": h / math.log2(obj.n)})
+            else:
+                worst = None
+                for b in range(obj.B):
+                    v0, v1 = int(obj.voff[b]), int(obj.voff[b + 1])
+                    if v1 - v0 < 2:
+                        continue
+                    h = oracle.dendrogram_height(ep[v0 - b:v1 - b - 1], vp[v0:v1])
+                    r = h / math.log2(v1 - v0)
+                    if worst is None or r > worst["imb"]:
+                        worst = {"n": v1 - v0, "height": h, "imb": r, "tree": b}
+                imb.append(worst)
+        out["config"]["imbalance"] = imb
         out["cpu_baseline"] = {"value": total_edges / cpu_s, "unit": "edges/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"one full step of {args.workload} ({total_edges} edges), "

@@ -56,6 +56,8 @@ def _load():
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p]
     lib.oracle_dendrogram_batched.restype = ctypes.c_int
+    lib.oracle_dendrogram_height.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_dendrogram_height.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -116,3 +118,14 @@ def dendrogram_batched(voff, u, v, w):
     if st:
         raise OracleError(st)
     return ep, vp
+
+
+def dendrogram_height(edge_parent, vertex_parent) -> int:
+    """Largest number of edge nodes from a vertex up to the root (the paper's
+    imbalance is this over log2 n)."""
+    ep = np.ascontiguousarray(edge_parent, dtype=np.int32)
+    vp = np.ascontiguousarray(vertex_parent, dtype=np.int32)
+    h = _load().oracle_dendrogram_height(len(vp), _ptr(ep), _ptr(vp))
+    if h < 0:
+        raise OracleError(1)
+    return int(h)

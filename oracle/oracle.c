@@ -183,3 +183,55 @@ int oracle_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u, 
     }
     return ORC_OK;
 }
+
+/*
+ * Height of a dendrogram: the largest number of edge nodes on the path from a
+ * vertex up to the root.  The paper's imbalance measure (Section 6, Table 2)
+ * divides it by log2 n: near 1 for a balanced dendrogram, about n / log2 n
+ * for a single chain.  Depths are filled iteratively: climb from an edge to
+ * the first edge of known depth (or past the root), then walk the same path
+ * again writing depths.  Returns -1 for malformed parents (an id out of
+ * range, or a cycle).
+ */
+int64_t oracle_dendrogram_height(int64_t n, const int32_t* edge_parent, const int32_t* vertex_parent)
+{
+    if (n < 1 || !vertex_parent) return -1;
+    if (n == 1) return 0;
+    if (!edge_parent) return -1;
+    const int64_t m = n - 1;
+    int64_t* depth = (int64_t*)calloc((size_t)m, sizeof(int64_t));   /* 0 = not known yet */
+    if (!depth) return -1;
+    int64_t height = -1;
+    for (int64_t e = 0; e < m; ++e) {
+        if (depth[e]) continue;
+        int64_t k = 0, base = 0, x = e;
+        for (;;) {
+            if (x < 0 || x >= m || k > m) goto bad;
+            if (depth[x]) {
+                base = depth[x];
+                break;
+            }
+            ++k;
+            if (edge_parent[x] == -1) {
+                base = 0;
+                break;
+            }
+            x = edge_parent[x];
+        }
+        x = e;
+        for (int64_t d = base + k; d > base; --d) {
+            depth[x] = d;
+            x = edge_parent[x];
+        }
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        const int32_t p = vertex_parent[v];
+        if (p < 0 || p >= m) goto bad;
+        if (depth[p] > height) height = depth[p];
+    }
+    free(depth);
+    return height;
+bad:
+    free(depth);
+    return -1;
+}

@@ -143,6 +143,35 @@ def test_bitreverse_path_is_perfect_binary(levels):
     assert invariants(n, t.u, t.v, t.w, ep, vp) == levels
 
 
+# ---- dendrogram height (numerator of the paper's imbalance, Table 2) ----
+
+@pytest.mark.parametrize("maker, want", [
+    (lambda: gen.star(1000, 3), 999),           # one chain (Theorem lowerbound)
+    (lambda: gen.path_mono(5000), 4999),        # one chain
+    (lambda: gen.path_bitrev(10), 10),          # perfect binary: log2 n
+    (lambda: gen.rrt(2, 0), 1),
+])
+def test_height_closed_forms(maker, want):
+    t = maker()
+    ep, vp = _run(t)
+    assert oracle.dendrogram_height(ep, vp) == want
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_height_matches_independent_checker(seed):
+    t = gen.shuffled(gen.rrt(4000, seed), seed) if seed % 2 else gen.caterpillar(4000, None, 1e-3, seed)
+    ep, vp = _run(t)
+    assert oracle.dendrogram_height(ep, vp) == invariants(t.n, t.u, t.v, t.w, ep, vp)
+
+
+def test_height_degenerate_and_malformed():
+    assert oracle.dendrogram_height(np.empty(0, np.int32), np.array([-1], np.int32)) == 0
+    with pytest.raises(oracle.OracleError):      # a parent cycle
+        oracle.dendrogram_height(np.array([1, 0], np.int32), np.array([0, 0, 1], np.int32))
+    with pytest.raises(oracle.OracleError):      # a parent out of range
+        oracle.dendrogram_height(np.array([5, -1], np.int32), np.array([0, 0, 1], np.int32))
+
+
 # ---- library routine: scipy single linkage on the subdominant ultrametric ----
 
 @pytest.mark.parametrize("seed", range(12))
