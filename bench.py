@@ -360,6 +360,18 @@ def main():
                         worst = {"n": v1 - v0, "height": h, "imb": r, "tree": b}
                 imb.append(worst)
         out["config"]["imbalance"] = imb
+        # The multithreaded CPU form of the same method (single trees only),
+        # checked against the oracle's output on the same inputs.
+        if all(kind == "tree" for kind, _ in items):
+            from paper_2401_06089_amd import cpu as pcpu
+            threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+            t2 = time.perf_counter()
+            mt = [pcpu.dendrogram(obj.n, obj.u, obj.v, obj.w, threads=threads) for _, obj in items]
+            mt_s = time.perf_counter() - t2
+            ok = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(mt, results))
+            out["cpu_pandora_mt"] = {"value": total_edges / mt_s, "unit": "edges/s", "threads": threads,
+                                     "seconds": mt_s, "matches_oracle": ok,
+                                     "speedup_vs_oracle": cpu_s / mt_s}
         out["cpu_baseline"] = {"value": total_edges / cpu_s, "unit": "edges/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"one full step of {args.workload} ({total_edges} edges), "

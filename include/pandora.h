@@ -86,15 +86,62 @@ PANDORA_API int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const
                                const float* w, int32_t* edge_parent, int32_t* vertex_parent,
                                void* hip_stream);
 
-/* Device scratch bytes a call with n_total_vertices over B trees needs
- * (admission control and preallocation).  0 on invalid sizes. */
+/*
+ * Stream-ordered variants of the two calls above (same arguments, same
+ * results).  They enqueue the whole computation on hip_stream and return
+ * without waiting for the device: the contraction levels run without host
+ * round trips.
+ *   - Argument errors come back at once.
+ *   - Input errors (NOT_A_TREE, NAN_WEIGHT, BAD_VERTEX) are recorded on the
+ *     device and returned later by pandora_stream_status; the outputs of a
+ *     failed call are unspecified.
+ *   - u, v, w and the outputs must stay valid until the stream has passed
+ *     the call.  voff (host memory) is read before the call returns.
+ *   - Calls on one stream run in stream order and share its scratch.  A call
+ *     that needs more scratch than the stream holds waits for the stream once
+ *     while the scratch grows.
+ *   - No statistics (pandora_last_stats) or profiler events are kept.
+ */
+PANDORA_API int pandora_dendrogram_async(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                                         int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream);
+PANDORA_API int pandora_dendrogram_batched_async(int32_t B, const int64_t* voff, const int32_t* u,
+                                                 const int32_t* v, const float* w, int32_t* edge_parent,
+                                                 int32_t* vertex_parent, void* hip_stream);
+
+/*
+ * Waits for hip_stream, then returns the deferred status of the
+ * stream-ordered calls made on it since the last read, and clears it.
+ * PANDORA_OK if none failed.  If several failed, their errors are merged and
+ * the most specific status is returned (BAD_VERTEX, then NAN_WEIGHT, then
+ * NOT_A_TREE).  PANDORA_ERR_HIP if the stream itself failed.
+ */
+PANDORA_API int pandora_stream_status(void* hip_stream);
+
+/*
+ * Caller-owned scratch for the calls made on hip_stream (current device).
+ *   dev_ptr  256-byte aligned device memory of `bytes` bytes, or NULL to go
+ *            back to scratch the library allocates.
+ * Calls on that stream that need more than `bytes` (see
+ * pandora_workspace_bytes) return PANDORA_ERR_OUT_OF_MEMORY.  The library
+ * never frees the caller's buffer.  This waits for the stream first, since
+ * earlier calls may still use the previous buffer.
+ * pandora_release_workspaces drops the setting.  A small status word and
+ * pinned host staging stay library-owned.  Returns INVALID_ARG for a
+ * misaligned pointer or zero bytes.
+ */
+PANDORA_API int pandora_set_workspace(void* hip_stream, void* dev_ptr, size_t bytes);
+
+/* Device scratch bytes a call with n_total_vertices over B trees needs under
+ * any tuning (admission control, preallocation, pandora_set_workspace).  0 on
+ * invalid sizes and for forests with no edges. */
 PANDORA_API size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B);
 
 /* Per-stage statistics of the last successful call on this thread:
  * out[0] = levels, out[1] = sum of edges over all levels, out[2] = pointer
  * jumping launches, out[3] = levels done in the LDS tail, out[4] = edges at
  * the level the LDS tail started from, out[5] = 1 if the call ran without
- * host round trips.  Returns the number filled (<= cap), or
+ * host round trips, out[6] = 1 if some levels ran in the persistent level
+ * kernel.  Returns the number filled (<= cap), or
  * -PANDORA_ERR_INVALID_ARG for a NULL out or a negative cap. */
 PANDORA_API int pandora_last_stats(int64_t* out, int cap);
 
@@ -108,6 +155,10 @@ PANDORA_API int pandora_last_stats(int64_t* out, int cap);
  *                        8 [0]
  *   sort_tile_cfg        radix tile: 0..3 = 1024, 2048, 4096, 8192 keys per
  *                        workgroup [3]
+ *   persist_max_edges    levels with at most this many edges run in one
+ *                        persistent launch (one workgroup per compute unit,
+ *                        grid barriers between the steps of a level) instead
+ *                        of one launch per step; 0 turns it off [262144]
  * pandora_set_tuning returns INVALID_ARG for out-of-range values.
  * pandora_set_thread_tuning overrides them for calls made by the calling
  * thread only (NULL removes the override), so concurrent callers can tune
@@ -117,6 +168,7 @@ typedef struct {
     int32_t jump_steps;
     int32_t chain_digit_bits;
     int32_t sort_tile_cfg;
+    int32_t persist_max_edges;
 } pandora_tuning_t;
 PANDORA_API int pandora_set_tuning(const pandora_tuning_t* t);
 PANDORA_API int pandora_get_tuning(pandora_tuning_t* t);

@@ -42,7 +42,8 @@ _lib = None
 class Tuning(ctypes.Structure):
     """Mirror of pandora_tuning_t (speed knobs only; results never change)."""
     _fields_ = [("sync_free_max_edges", ctypes.c_int32), ("jump_steps", ctypes.c_int32),
-                ("chain_digit_bits", ctypes.c_int32), ("sort_tile_cfg", ctypes.c_int32)]
+                ("chain_digit_bits", ctypes.c_int32), ("sort_tile_cfg", ctypes.c_int32),
+                ("persist_max_edges", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -90,6 +91,14 @@ def _load():
     lib.pandora_graph_destroy.restype = None
     lib.pandora_status_string.argtypes = [ctypes.c_int]
     lib.pandora_status_string.restype = ctypes.c_char_p
+    lib.pandora_dendrogram_async.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.pandora_dendrogram_async.restype = ctypes.c_int
+    lib.pandora_dendrogram_batched_async.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+    lib.pandora_dendrogram_batched_async.restype = ctypes.c_int
+    lib.pandora_stream_status.argtypes = [vp]
+    lib.pandora_stream_status.restype = ctypes.c_int
+    lib.pandora_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.pandora_set_workspace.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -213,14 +222,97 @@ def dendrogram_batched(voff, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
     return ep, vp
 
 
+def _hold_for(stream, dev, *tensors):
+    """The caching allocator may reuse a tensor's memory as soon as its last
+    reference is gone, judged by the stream it was allocated on.  A
+    stream-ordered call reads and writes later, on `stream`: tie every tensor
+    it uses to that stream so that no memory is reused before it has run."""
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    for t in tensors:
+        if t is not None and t.numel() > 0:
+            t.record_stream(s)
+
+
+def dendrogram_async(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, n: Optional[int] = None,
+                     stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Stream-ordered dendrogram: enqueues the call and returns at once.
+
+    The outputs are valid once the stream has passed the call; input errors
+    are reported by stream_status(stream).  Every tensor the call uses is tied
+    to the stream, so the caller may drop its references right away."""
+    m = w.numel()
+    if n is None:
+        n = m + 1
+    if n != m + 1 or u.numel() != m or v.numel() != m:
+        raise ValueError("a tree with n vertices has n-1 edges")
+    dev = w.device
+    u = _as_dev(u, torch.int32, dev)
+    v = _as_dev(v, torch.int32, dev)
+    w = _as_dev(w, torch.float32, dev)
+    with torch.cuda.device(dev):
+        ep = torch.empty(m, dtype=torch.int32, device=dev)
+        vp = torch.empty(n, dtype=torch.int32, device=dev)
+        _apply_tuning(m)
+        _check(_load().pandora_dendrogram_async(int(n), _dptr(u), _dptr(v), _dptr(w), _dptr(ep), _dptr(vp),
+                                                _stream_handle(stream)))
+        _hold_for(stream, dev, u, v, w, ep, vp)
+    return ep, vp
+
+
+def dendrogram_batched_async(voff, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
+                             stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Stream-ordered dendrogram_batched (see dendrogram_async)."""
+    voff_t = torch.as_tensor(voff, dtype=torch.int64).cpu().contiguous()
+    B = voff_t.numel() - 1
+    if B < 1:
+        raise ValueError("need at least one tree")
+    N = int(voff_t[-1])
+    M = N - B
+    if w.numel() != M or u.numel() != M or v.numel() != M:
+        raise ValueError("edge arrays must hold voff[-1] - B entries")
+    dev = w.device
+    u = _as_dev(u, torch.int32, dev)
+    v = _as_dev(v, torch.int32, dev)
+    w = _as_dev(w, torch.float32, dev)
+    with torch.cuda.device(dev):
+        ep = torch.empty(M, dtype=torch.int32, device=dev)
+        vp = torch.empty(N, dtype=torch.int32, device=dev)
+        _apply_tuning(M)
+        _check(_load().pandora_dendrogram_batched_async(
+            B, ctypes.c_void_p(voff_t.data_ptr()), _dptr(u), _dptr(v), _dptr(w), _dptr(ep), _dptr(vp),
+            _stream_handle(stream)))
+        _hold_for(stream, dev, u, v, w, ep, vp)
+    return ep, vp
+
+
+def stream_status(stream=None) -> int:
+    """Waits for the stream; returns (and clears) the deferred status of its
+    stream-ordered calls."""
+    return int(_load().pandora_stream_status(_stream_handle(stream)))
+
+
+def set_workspace(buffer: Optional[torch.Tensor], stream=None) -> None:
+    """Caller-owned scratch for calls on `stream` (a device tensor of at least
+    workspace_bytes(...) bytes, 256-byte aligned), or None to return to
+    library-owned scratch.  Keep the tensor alive while it is installed."""
+    if buffer is None:
+        _check(_load().pandora_set_workspace(_stream_handle(stream), None, 0))
+        return
+    if buffer.device.type != "cuda" or not buffer.is_contiguous():
+        raise ValueError("the workspace must be a contiguous device tensor")
+    nbytes = buffer.numel() * buffer.element_size()
+    _check(_load().pandora_set_workspace(_stream_handle(stream), ctypes.c_void_p(buffer.data_ptr()), nbytes))
+
+
 def workspace_bytes(n_total_vertices: int, trees: int = 1) -> int:
     return int(_load().pandora_workspace_bytes(int(n_total_vertices), int(trees)))
 
 
 def last_stats() -> dict:
-    buf = (ctypes.c_int64 * 6)()
-    k = _load().pandora_last_stats(buf, 6)
-    names = ["levels", "sum_level_edges", "jump_launches", "tail_levels", "tail_entry_edges", "sync_free"]
+    buf = (ctypes.c_int64 * 7)()
+    k = _load().pandora_last_stats(buf, 7)
+    names = ["levels", "sum_level_edges", "jump_launches", "tail_levels", "tail_entry_edges", "sync_free",
+             "persistent"]
     return {names[i]: int(buf[i]) for i in range(k)}
 
 

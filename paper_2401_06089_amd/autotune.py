@@ -35,6 +35,7 @@ KNOBS = {
     "jump_steps": [4, 8, 16, 32],
     "chain_digit_bits": [8, 9],
     "sync_free_max_edges": [0, 2**31 - 1],
+    "persist_max_edges": [0, 1 << 16, 1 << 18, 1 << 20],
 }
 
 DEFAULT_SIZES = [1_000, 10_000, 100_000, 1_000_000, 10_000_000]
@@ -128,7 +129,10 @@ def install(table: Optional[dict]) -> None:
         _table = None
         _set_tuning_hook(None)
         return
-    _table = sorted(table["buckets"], key=lambda b: b["max_edges"])
+    # knobs a table does not name keep the process-wide values
+    base = get_tuning()
+    _table = sorted(({**b, "tuning": {**base, **b["tuning"]}} for b in table["buckets"]),
+                    key=lambda b: b["max_edges"])
     _set_tuning_hook(pick)
 
 

@@ -36,6 +36,7 @@ struct Control {
     int32_t n_next;           // leaf edges at the current level   (= n_{j+1})
     int32_t tail_levels;      // levels finished inside the LDS tail kernel
     int32_t tail_vertices;    // vertices of the last level (all isolated)
+    uint32_t grid_bar;        // arrivals at the persistent level kernel's grid barriers
     uint32_t sort_tiles[8];   // dynamic tile counters, one per radix pass
     LevelInfo lv[kMaxLevels]; // level sizes (lv[0] set at the start of a call)
     uint32_t hist[8][512];    // per-pass digit histograms (8- or 9-bit digits)

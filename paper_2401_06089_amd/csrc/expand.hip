@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
     a.edge_parent[id] = parent;
 }
 
-__global__ void k_zero_control(Control* c, int32_t m, int32_t n) {
+__global__ void k_zero_control(Control* c, int32_t m, int32_t n, int64_t* voff1) {
     uint32_t* p = reinterpret_cast<uint32_t*>(c);
     const int words = (int)(sizeof(Control) / sizeof(uint32_t));
     for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
@@ -85,7 +85,24 @@ __global__ void k_zero_control(Control* c, int32_t m, int32_t n) {
         c->lv[0].m = m;
         c->lv[0].n = n;
         c->lv[0].off = 0;
+        if (voff1) {            // a single tree: its offsets need no copy from the host
+            voff1[0] = 0;
+            voff1[1] = n;
+        }
     }
+}
+
+// End of a stream-ordered call: its input errors (and a component count other
+// than the number of trees) are OR-ed into the stream's sticky status word.
+__global__ void k_finalize(const Control* c, int32_t B, uint32_t* sticky) {
+    if (threadIdx.x != 0) return;
+    uint32_t e = c->err;
+    if (e == 0 && (int64_t)c->isolated != B) e = kErrNotTree;
+    if (e) atomicOr(sticky, e);
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t value) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = value;
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t value) {
@@ -109,8 +126,18 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_zero_control(Control* c, int32_t m, int32_t n, hipStream_t s) {
-    k_zero_control<<<1, 256, 0, s>>>(c, m, n);
+hipError_t launch_finalize(const Control* c, int32_t B, uint32_t* sticky, hipStream_t s) {
+    k_finalize<<<1, 64, 0, s>>>(c, B, sticky);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_words(uint32_t* p, int64_t n, hipStream_t s) {
+    k_fill_u32<<<1, 256, 0, s>>>(p, n, 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_control(Control* c, int32_t m, int32_t n, int64_t* voff1, hipStream_t s) {
+    k_zero_control<<<1, 256, 0, s>>>(c, m, n, voff1);
     return hipGetLastError();
 }
 

@@ -127,7 +127,22 @@ __host__ __device__ inline bool tail_level(int64_t m, int64_t n, int tail_e, int
     return m == 0 || (m <= tail_e && n <= tail_v);
 }
 
-hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s);
+hipError_t launch_min_incident(const LevelArgs& a, hipStream_t s);
+
+// Levels [first_level, last_level) in one persistent launch (stops at the
+// first level small enough for the LDS tail).  a holds the pointers shared by
+// all levels; the per-level fields are filled from the capacities.
+struct PersistArgs {
+    LevelArgs a;
+    EdgeRec* E0;
+    EdgeRec* EA;
+    EdgeRec* EB;
+    int32_t first_level, last_level;
+    int32_t jump_rounds;     // pointer-jumping rounds; the last is bounded only by the level size
+    int32_t capE[kMaxLevels + 1];
+    int32_t capV[kMaxLevels + 1];
+};
+hipError_t launch_levels(const PersistArgs& p, int grid, hipStream_t s);
 hipError_t launch_own(bool level0, const LevelArgs& a, hipStream_t s);
 hipError_t launch_classify(const LevelArgs& a, hipStream_t s);
 hipError_t launch_jump(const LevelArgs& a, hipStream_t s);
@@ -187,7 +202,11 @@ hipError_t launch_walk_hist(const WalkArgs& a, hipStream_t s);
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t s);
 
 // ---- misc -----------------------------------------------------------------------
-hipError_t launch_zero_control(Control* c, int32_t m, int32_t n, hipStream_t s);
+// Clears the control block; voff1, if given, receives the offsets {0, n} of a
+// single tree.
+hipError_t launch_zero_control(Control* c, int32_t m, int32_t n, int64_t* voff1, hipStream_t s);
+hipError_t launch_finalize(const Control* c, int32_t B, uint32_t* sticky, hipStream_t s);
+hipError_t launch_clear_words(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s);
 
 }  // namespace pandora

@@ -7,11 +7,13 @@
 // levels in compaction order.  Every comparison uses ranks, never positions.
 //
 // One level, m_j edges and n_j vertices:
-//   k_min_incident  min64[x] = min over incident edges of (rank << 32 | pos):
-//                   the lightest incident edge (Eq. vertexparent) and where
-//                   its record lives.  At level 0 it also builds the 16-byte
-//                   edge records from the caller's arrays, translating the
-//                   tree-local ids of a forest and validating them.
+//   k_min_incident  (level 0) min64[x] = min over incident edges of
+//                   (rank << 32 | pos): the lightest incident edge (Eq.
+//                   vertexparent) and where its record lives.  It also builds
+//                   the 16-byte edge records from the caller's arrays,
+//                   translating the tree-local ids of a forest and validating
+//                   them.  Deeper levels get the same minima from the
+//                   compaction that writes their edges.
 //   k_own           per vertex: one gather of its lightest edge's record gives
 //                   the hook ptr[x] = other endpoint, the rank table entry and
 //                   (level 0) the vertex's dendrogram parent; the vertex marks
@@ -27,7 +29,8 @@
 //                   host relaunches until every vertex has its label); each
 //                   vertex writes its flat label and records its lightest
 //                   edge's supervertex for the expansion.
-//   k_compact       stable compaction of alpha edges, endpoints relabelled.
+//   k_compact       stable compaction of alpha edges, endpoints relabelled;
+//                   each written edge also bids for the next level's minima.
 //
 // Vertices of all levels share one flat id space: level j occupies
 // [off_j, off_j + n_j).  Isolated vertices (finished components of a forest)
@@ -117,7 +120,6 @@ __device__ uint64_t wave_lookback(const uint64_t* lb, int64_t tile, Control* ctr
 
 // After an input error every level kernel returns at once: the call's outputs
 // are unspecified then, and nothing may index with the damaged tables.
-template <bool L0>
 __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
     const LevelView L = level_view(a);
     if (L.skip || a.ctrl->err) return;
@@ -128,26 +130,22 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
         a.ctrl->not_converged = 0;
     }
     if (i >= L.m) return;
-    EdgeRec e;
-    if (L0) {
-        const int32_t b = a.forest.tree_of_edge(i);
-        const int64_t v0 = a.forest.voff[b];
-        const int64_t nb = a.forest.voff[b + 1] - v0;
-        int64_t x = a.in_u[i];
-        int64_t y = a.in_v[i];
-        if (x < 0 || x >= nb || y < 0 || y >= nb) {
-            raise_err(a.ctrl, kErrBadVertex);
-            x = (x < 0 || x >= nb) ? 0 : x;
-            y = (y < 0 || y >= nb) ? 0 : y;
-        }
-        e.u = (int32_t)(v0 + x);
-        e.v = (int32_t)(v0 + y);
-        e.r = a.rank[i];
-        e.id = (int32_t)i;
-        a.E[i] = e;
-    } else {
-        e = a.E[i];
+    const int32_t b = a.forest.tree_of_edge(i);
+    const int64_t v0 = a.forest.voff[b];
+    const int64_t nb = a.forest.voff[b + 1] - v0;
+    int64_t x = a.in_u[i];
+    int64_t y = a.in_v[i];
+    if (x < 0 || x >= nb || y < 0 || y >= nb) {
+        raise_err(a.ctrl, kErrBadVertex);
+        x = (x < 0 || x >= nb) ? 0 : x;
+        y = (y < 0 || y >= nb) ? 0 : y;
     }
+    EdgeRec e;
+    e.u = (int32_t)(v0 + x);
+    e.v = (int32_t)(v0 + y);
+    e.r = a.rank[i];
+    e.id = (int32_t)i;
+    a.E[i] = e;
     const uint64_t key = ((uint64_t)(uint32_t)e.r << 32) | (uint64_t)(uint32_t)i;
     // Read first: values only decrease, so a stale read can only cause a
     // redundant atomic, never a missed one.
@@ -155,12 +153,13 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
     if (a.min64[e.v] > key) atomicMin((unsigned long long*)&a.min64[e.v], (unsigned long long)key);
 }
 
+// ---- per-item and per-tile bodies ---------------------------------------------
+// Shared by the per-level kernels below and by the persistent kernel k_levels.
+
+// One vertex x (x >= L.n is a no-op; called by whole waves).
 template <bool L0>
-__global__ __launch_bounds__(256) void k_own(LevelArgs a) {
-    const LevelView L = level_view(a);
-    if (L.skip || a.ctrl->err) return;
+__device__ __forceinline__ void own_item(const LevelArgs& a, const LevelView& L, int64_t x) {
     VInfo* vinfo = a.vinfo_all + L.off;
-    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool live = x < L.n;
     const uint64_t mm = live ? a.min64[x] : 0;
     const bool isolated = live && mm == kNoEdge;
@@ -189,25 +188,14 @@ __global__ __launch_bounds__(256) void k_own(LevelArgs a) {
     }
 }
 
-// Level 0 and the deeper levels get separate instantiations of the remaining
-// kernels too, so that per-kernel profiles separate the two (their sizes
-// differ by the contraction factor).
+// One claimed scan tile of the alpha/leaf classification (whole workgroup).
 template <bool L0>
-__global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
+__device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelView& L, int64_t tile) {
     constexpr int W = kScanBlock / kWave;
     __shared__ uint32_t s_ca[kScanItems][W];
     __shared__ uint32_t s_cl[kScanItems][W];
     __shared__ uint64_t s_excl;
-    __shared__ uint32_t s_tile;
-    const LevelView L = level_view(a);
-    // The error check comes before a tile is claimed: a claimed tile is always
-    // finished, so no claimed tile ever waits on a tile that nobody claimed.
-    if (L.skip || a.ctrl->err) return;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    if (tid == 0) s_tile = atomicAdd(&a.ctrl->alpha_tiles, 1u);
-    __syncthreads();
-    const int64_t tile = s_tile;
-    if (tile >= scan_tiles(L.m)) return;       // surplus workgroup of a capacity-sized grid
     const int64_t base = tile * kScanTile;
     const uint64_t lt = lanemask_lt();
 
@@ -293,24 +281,18 @@ __global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
     }
 }
 
-template <bool L0>
-__global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
-    const LevelView L = level_view(a);
-    if (L.skip) return;
-    // a later round runs only if the previous one left some vertex unresolved
-    if (a.round > 0 && !(a.ctrl->not_converged & (1u << ((a.round - 1) & 31)))) return;
-    if (a.ctrl->err) return;                     // invalid input: outputs are unspecified
+// One vertex x < L.n, one pointer-jumping round of at most `steps` steps.
+__device__ __forceinline__ void jump_item(const LevelArgs& a, const LevelView& L, int64_t x, int round,
+                                          int steps) {
     VInfo* vinfo = a.vinfo_all + L.off;
-    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (x >= L.n) return;
-    if (a.round == 0) {
+    if (round == 0) {
         int32_t nn = a.ctrl->lv[a.level + 1].n;
         if (nn > a.cap_next_v) nn = a.cap_next_v;
         if (x < nn) a.min64[x] = kNoEdge;     // the next level starts clean
     }
     const int32_t r = vinfo[x].minInc;
     if (r == kInf) {
-        if (a.round == 0) vinfo[x].label = -1;
+        if (round == 0) vinfo[x].label = -1;
         return;
     }
     int32_t q = a.ptr[x];
@@ -319,13 +301,13 @@ __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
         lab = q & ~kLabelFlag;
     } else {
         int32_t t = a.ptr[q];
-        for (int s = 0; !(t & kLabelFlag) && s < a.jump_steps; ++s) {
+        for (int s = 0; !(t & kLabelFlag) && s < steps; ++s) {
             q = t;
             t = a.ptr[q];
         }
         if (!(t & kLabelFlag)) {
-            a.ptr[x] = q;                        // progress for the next launch
-            atomicOr(&a.ctrl->not_converged, 1u << (a.round & 31));
+            a.ptr[x] = q;                        // progress for the next round
+            atomicOr(&a.ctrl->not_converged, 1u << (round & 31));
             return;
         }
         lab = t & ~kLabelFlag;
@@ -336,15 +318,36 @@ __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
     a.svflat[r] = flat;                          // the lightest edge of x falls into this supervertex
 }
 
+// Sizes of the level after a (written by its classification), clamped.
+struct NextSizes {
+    int32_t m, n;
+};
+__device__ __forceinline__ NextSizes next_sizes(const LevelArgs& a) {
+    const bool has_next = a.level + 1 < kMaxLevels;
+    int32_t n_next = has_next ? a.ctrl->lv[a.level + 1].n : 0;
+    int32_t m_next = has_next ? a.ctrl->lv[a.level + 1].m : 0;
+    n_next = n_next < a.cap_next_v ? n_next : a.cap_next_v;
+    m_next = m_next < a.cap_next_e ? m_next : a.cap_next_e;
+    return {m_next, n_next};
+}
+
+// Before the compaction: the next level's scan starts clean (this level's scan
+// is finished) and the scan counters restart.  g is a global thread index.
+__device__ __forceinline__ void compact_prepare(const LevelArgs& a, const NextSizes& nx, int64_t g) {
+    if (g < scan_tiles(nx.m)) a.scan_lb[g] = 0;
+    if (g == 0) {
+        a.ctrl->alpha_tiles = 0;
+        a.ctrl->not_converged = 0;
+    }
+}
+
+// One tile of the stable alpha compaction (whole workgroup).
 template <bool L0>
-__global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
+__device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView& L, const NextSizes& nx,
+                                             int64_t tile) {
     constexpr int W = kScanBlock / kWave;
     __shared__ uint32_t s_ca[kScanItems][W];
-    const LevelView L = level_view(a);
-    if (L.skip || a.ctrl->err) return;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    const int64_t tile = blockIdx.x;
-    if (tile >= scan_tiles(L.m)) return;
     const VInfo* vinfo = a.vinfo_all + L.off;
     const int64_t base = tile * kScanTile;
     const uint64_t lt = lanemask_lt();
@@ -381,19 +384,183 @@ __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
         const int32_t ly = vinfo[e.v].label;
         const int64_t pos = abase + s_ca[k][wave] + apre[k];
         selfloop |= lx == ly;
-        if (pos < a.cap_next_e) {
+        const int64_t ux = (int64_t)lx - L.off_next, vx = (int64_t)ly - L.off_next;
+        if (pos < nx.m && ux >= 0 && ux < nx.n && vx >= 0 && vx < nx.n) {
             EdgeRec o;
-            o.u = (int32_t)(lx - L.off_next);
-            o.v = (int32_t)(ly - L.off_next);
+            o.u = (int32_t)ux;
+            o.v = (int32_t)vx;
             o.r = e.r;
             o.id = 0;
             a.out[pos] = o;
+            // The next level's lightest incident edges (its min64 words were
+            // reset by this level's pointer jumping): read first, values only
+            // decrease.
+            const uint64_t key = ((uint64_t)(uint32_t)e.r << 32) | (uint64_t)pos;
+            if (a.min64[ux] > key) atomicMin((unsigned long long*)&a.min64[ux], (unsigned long long)key);
+            if (a.min64[vx] > key) atomicMin((unsigned long long*)&a.min64[vx], (unsigned long long)key);
         } else {
             overflow = true;
         }
     }
     if (ballot(selfloop) != 0 && lane == 0) raise_err(a.ctrl, kErrNotTree);
     if (ballot(overflow) != 0 && lane == 0) raise_err(a.ctrl, kErrOverflow);
+    __syncthreads();   // s_ca is reused by the workgroup's next tile
+}
+
+// ---- one kernel per step and level ----------------------------------------------
+
+template <bool L0>
+__global__ __launch_bounds__(256) void k_own(LevelArgs a) {
+    const LevelView L = level_view(a);
+    if (L.skip || a.ctrl->err) return;
+    own_item<L0>(a, L, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// Level 0 and the deeper levels get separate instantiations of the remaining
+// kernels too, so that per-kernel profiles separate the two (their sizes
+// differ by the contraction factor).
+template <bool L0>
+__global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
+    __shared__ uint32_t s_tile;
+    const LevelView L = level_view(a);
+    // The error check comes before a tile is claimed: a claimed tile is always
+    // finished, so no claimed tile ever waits on a tile that nobody claimed.
+    if (L.skip || a.ctrl->err) return;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&a.ctrl->alpha_tiles, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= scan_tiles(L.m)) return;       // surplus workgroup of a capacity-sized grid
+    classify_tile<L0>(a, L, tile);
+}
+
+template <bool L0>
+__global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
+    const LevelView L = level_view(a);
+    if (L.skip) return;
+    // a later round runs only if the previous one left some vertex unresolved
+    if (a.round > 0 && !(a.ctrl->not_converged & (1u << ((a.round - 1) & 31)))) return;
+    if (a.ctrl->err) return;                     // invalid input: outputs are unspecified
+    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= L.n) return;
+    jump_item(a, L, x, a.round, a.jump_steps);
+}
+
+template <bool L0>
+__global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
+    const LevelView L = level_view(a);
+    if (L.skip || a.ctrl->err) return;
+    const NextSizes nx = next_sizes(a);
+    // the grid has at least as many threads as the next level has scan tiles
+    compact_prepare(a, nx, (int64_t)blockIdx.x * kScanBlock + threadIdx.x);
+    const int64_t tile = blockIdx.x;
+    if (tile >= scan_tiles(L.m)) return;
+    compact_tile<L0>(a, L, nx, tile);
+}
+
+// ---- persistent kernel: all mid-size levels in one launch -------------------------
+//
+// One workgroup per CU walks through the levels; grid barriers separate the
+// steps.  Every decision that shapes the loop (a level's size, whether pointer
+// jumping converged) is read after a barrier from words written before it, so
+// all workgroups take the same path.  Barrier waits are bounded and stop once
+// an input error is flagged (then every step returns at once and the outputs
+// are unspecified anyway).
+
+__device__ __forceinline__ void grid_barrier(Control* c, uint32_t& target) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        target += gridDim.x;
+        __threadfence();
+        atomicAdd(&c->grid_bar, 1u);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&c->grid_bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (++spins > kSpinLimit) {
+                raise_err(c, kErrSpin);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool err_set(Control* c) {
+    return __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+template <bool L0>
+__device__ void persistent_level(const LevelArgs& a, const LevelView& L, int jump_rounds, uint32_t& bar,
+                                 uint32_t* s_tile) {
+    Control* c = a.ctrl;
+    const int tid = threadIdx.x;
+    const int64_t gsize = (int64_t)gridDim.x * kScanBlock;
+    const int64_t gtid = (int64_t)blockIdx.x * kScanBlock + tid;
+
+    // 1. ownership: whole waves step through the vertices together
+    if (!err_set(c))
+        for (int64_t xb = gtid - lane_id(); xb < L.n; xb += gsize) own_item<L0>(a, L, xb + lane_id());
+    grid_barrier(c, bar);
+
+    // 2. alpha / leaf classification and the label scan over claimed tiles
+    while (true) {
+        __syncthreads();
+        if (tid == 0) *s_tile = err_set(c) ? 0xffffffffu : atomicAdd(&c->alpha_tiles, 1u);
+        __syncthreads();
+        const uint32_t t = *s_tile;
+        if (t >= (uint32_t)scan_tiles(L.m)) break;
+        classify_tile<L0>(a, L, t);
+    }
+    grid_barrier(c, bar);
+
+    // 3. pointer jumping: bounded rounds, then one bounded only by the level size
+    for (int round = 0;; ++round) {
+        const bool last = round + 1 >= jump_rounds;
+        const int steps = last ? (L.n > 16 ? L.n : 16) : a.jump_steps;
+        // the bit of the next round is not read or written during this one
+        if (gtid == 0) atomicAnd(&c->not_converged, ~(1u << ((round + 1) & 31)));
+        if (!err_set(c))
+            for (int64_t x = gtid; x < L.n; x += gsize) jump_item(a, L, x, round, steps);
+        grid_barrier(c, bar);
+        const uint32_t nc = __hip_atomic_load(&c->not_converged, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!(nc & (1u << (round & 31)))) break;
+        if (last) {
+            if (gtid == 0) raise_err(c, kErrNotTree);   // only a cycle keeps a vertex from its root
+            break;
+        }
+    }
+
+    // 4. compaction into the next level (which also bids for its minima); the
+    // tiles hold workgroup barriers, so the whole workgroup takes one decision
+    const NextSizes nx = next_sizes(a);
+    __syncthreads();
+    if (tid == 0) *s_tile = err_set(c) ? 1u : 0u;
+    __syncthreads();
+    if (*s_tile == 0) {
+        for (int64_t g = gtid; g < scan_tiles(nx.m) || g == 0; g += gsize) compact_prepare(a, nx, g);
+        for (int64_t t = blockIdx.x; t < scan_tiles(L.m); t += gridDim.x) compact_tile<L0>(a, L, nx, t);
+    }
+    grid_barrier(c, bar);
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_levels(PersistArgs p) {
+    __shared__ uint32_t s_tile;
+    uint32_t bar = 0;
+    for (int j = p.first_level; j < p.last_level; ++j) {
+        LevelArgs a = p.a;
+        a.level = j;
+        a.cap_m = p.capE[j];
+        a.cap_n = p.capV[j];
+        a.cap_next_e = p.capE[j + 1];
+        a.cap_next_v = p.capV[j + 1];
+        a.E = j == 0 ? p.E0 : (j % 2 == 1 ? p.EA : p.EB);
+        a.out = j % 2 == 0 ? p.EA : p.EB;
+        const LevelView L = level_view(a);   // written before the last barrier: the same everywhere
+        if (L.skip) break;
+        if (j == 0) persistent_level<true>(a, L, p.jump_rounds, bar, &s_tile);
+        else persistent_level<false>(a, L, p.jump_rounds, bar, &s_tile);
+    }
 }
 
 // ---- the LDS tail: all remaining levels in one workgroup ----------------------
@@ -619,10 +786,9 @@ inline unsigned blocks_for(int64_t n, int per) {
 
 }  // namespace
 
-hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s) {
+hipError_t launch_min_incident(const LevelArgs& a, hipStream_t s) {
     const int64_t work = a.cap_m > scan_tiles(a.cap_m) ? a.cap_m : scan_tiles(a.cap_m);
-    if (level0) k_min_incident<true><<<blocks_for(work, 256), 256, 0, s>>>(a);
-    else k_min_incident<false><<<blocks_for(work, 256), 256, 0, s>>>(a);
+    k_min_incident<<<blocks_for(work, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -647,6 +813,11 @@ hipError_t launch_jump(const LevelArgs& a, hipStream_t s) {
 hipError_t launch_compact(const LevelArgs& a, hipStream_t s) {
     if (a.level == 0) k_compact<true><<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
     else k_compact<false><<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_levels(const PersistArgs& p, int grid, hipStream_t s) {
+    k_levels<<<grid, kScanBlock, 0, s>>>(p);
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -32,6 +33,7 @@ namespace {
 
 constexpr int kMaxJumpRounds = 64;
 constexpr int kSyncFreeJumpRounds = 3;   // the last one is bounded only by the level size
+constexpr int kPersistJumpRounds = 6;    // rounds inside the persistent level kernel (same rule)
 constexpr size_t kAlign = 256;
 constexpr size_t kCtrlReadback = 32;   // err .. tail_vertices
 constexpr size_t kCtrlLevelsReadback = offsetof(Control, hist);   // header + level table
@@ -43,6 +45,7 @@ pandora_tuning_t g_tune = {
     /*jump_steps=*/16,
     /*chain_digit_bits=*/0,
     /*sort_tile_cfg=*/kDefaultSortCfg,
+    /*persist_max_edges=*/1 << 18,
 };
 
 thread_local bool t_has_tune = false;
@@ -57,7 +60,21 @@ pandora_tuning_t current_tuning() {
 bool tuning_valid(const pandora_tuning_t* t) {
     return t->sync_free_max_edges >= 0 && t->jump_steps >= 1 && t->jump_steps <= 4096 &&
            (t->chain_digit_bits == 0 || t->chain_digit_bits == 8 || t->chain_digit_bits == 9) &&
-           t->sort_tile_cfg >= 0 && t->sort_tile_cfg < kNumSortCfg;
+           t->sort_tile_cfg >= 0 && t->sort_tile_cfg < kNumSortCfg && t->persist_max_edges >= 0;
+}
+
+// Compute units of a device (the persistent level kernel runs one workgroup
+// on each).
+int cu_count(int dev) {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 64;
+    cache[dev] = cus;
+    return cus;
 }
 
 struct Layout {
@@ -151,12 +168,27 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
     return L;
 }
 
+// Pinned staging for the offsets of a stream-ordered batched call: the copy
+// to the device runs later in stream order, so a slot is reused only once the
+// event after its copy has completed.
+constexpr int kStageSlots = 4;
+struct StageSlot {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
 struct Workspace {
     std::mutex mu;
     void* dev = nullptr;
     size_t bytes = 0;
+    bool owned = true;             // false: the caller's buffer (pandora_set_workspace)
     void* host = nullptr;          // pinned: Control readback + voff staging
     size_t host_bytes = 0;
+    uint32_t* sticky = nullptr;    // device: deferred status of stream-ordered calls
+    StageSlot stage[kStageSlots];
+    int next_stage = 0;
     hipStream_t stream = nullptr;
 };
 
@@ -165,7 +197,7 @@ std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
 
 struct Stats {
     int64_t levels = 0, sum_edges = 0, jump_launches = 0, tail_levels = 0, tail_entry_edges = 0,
-            sync_free = 0;
+            sync_free = 0, persistent = 0;
 };
 thread_local Stats g_last;
 
@@ -177,14 +209,14 @@ thread_local Stats g_last;
 enum ProfKind {
     PK_ZERO, PK_SORT_HIST, PK_SORT_W_FIRST, PK_SORT_W_MID, PK_SORT_W_LAST, PK_MIN_INC,
     PK_OWN, PK_CLASSIFY, PK_JUMP, PK_COMPACT, PK_TAIL, PK_WALK_HIST, PK_SORT_C_PASS, PK_STITCH,
-    PK_MIN_INC_N, PK_OWN_N, PK_CLASSIFY_N, PK_JUMP_N, PK_COMPACT_N,
+    PK_OWN_N, PK_CLASSIFY_N, PK_JUMP_N, PK_COMPACT_N, PK_LEVELS,
     PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "zero_control", "sort_hist", "sort_pass_weight_first", "sort_pass_weight_mid",
     "sort_pass_weight_last", "min_incident_l0", "own_l0", "classify_l0", "jump_l0", "compact_l0",
-    "tail", "walk_hist", "sort_pass_chain", "stitch", "min_incident_ln", "own_ln", "classify_ln",
-    "jump_ln", "compact_ln"};
+    "tail", "walk_hist", "sort_pass_chain", "stitch", "own_ln", "classify_ln", "jump_ln",
+    "compact_ln", "levels_persistent"};
 
 struct Prof {
     std::mutex mu;
@@ -276,6 +308,7 @@ int status_from_err(uint32_t err) {
     } while (0)
 
 int ensure(Workspace& ws, size_t dev_bytes, size_t host_bytes) {
+    if (!ws.owned && ws.bytes < dev_bytes) return PANDORA_ERR_OUT_OF_MEMORY;   // the caller's buffer is too small
     if (ws.bytes < dev_bytes) {
         if (ws.dev) {
             if (hipStreamSynchronize(ws.stream) != hipSuccess) return PANDORA_ERR_HIP;
@@ -332,7 +365,7 @@ size_t host_bytes_for(int32_t B) { return sizeof(Control) + sizeof(int64_t) * (B
 // (M >= 1 edges).  With sync_free nothing waits for the device before the
 // final readback in finish(), so the sequence can be captured in a graph.
 int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bool sync_free,
-            const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, const float* w,
+            const int64_t* staged_voff, int32_t B, const int32_t* u, const int32_t* v, const float* w,
             int32_t* edge_parent, int32_t* vertex_parent, hipStream_t s, Stats& st) {
     const int64_t N = L.N;
     const int64_t M = L.M;
@@ -340,10 +373,11 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
     void* d = sc.dev;
     Control* ctrl = at<Control>(d, L.ctrl);
     Control* hctrl = static_cast<Control*>(sc.host);
-    int64_t* hvoff = reinterpret_cast<int64_t*>(static_cast<char*>(sc.host) + sizeof(Control));
-    std::memcpy(hvoff, voff, sizeof(int64_t) * (B + 1));
+    // Tree offsets on the device: a single tree's are written by the first
+    // kernel; a forest's are copied from pinned staging that stays valid
+    // until the copy has run.
     int64_t* dvoff = at<int64_t>(d, L.voff);
-    PD_TRY(hipMemcpyAsync(dvoff, hvoff, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
+    if (B > 1) PD_TRY(hipMemcpyAsync(dvoff, staged_voff, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
     const Forest forest{dvoff, B};
 
     uint32_t* K[2] = {at<uint32_t>(d, L.K0), at<uint32_t>(d, L.K1)};
@@ -354,7 +388,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
     int32_t* svflat = at<int32_t>(d, L.svflat);
     const int64_t lb_words = L.lb_words_w;
 
-    PD_TIMED(PK_ZERO, sizeof(Control), launch_zero_control(ctrl, (int32_t)M, (int32_t)N, s));
+    PD_TIMED(PK_ZERO, sizeof(Control), launch_zero_control(ctrl, (int32_t)M, (int32_t)N, B == 1 ? dvoff : nullptr, s));
 
     // ---- 1. weight sort --------------------------------------------------------
     uint64_t* min64 = at<uint64_t>(d, L.min64);
@@ -433,6 +467,27 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         a.jump_steps = jump_steps;
         return a;
     };
+    // Levels of at most persist_max_edges edges run in one persistent launch
+    // (from level j on, until a level fits the LDS tail).
+    int dev = 0;
+    PD_TRY(hipGetDevice(&dev));
+    auto persistent_from = [&](int j) {
+        PersistArgs p{};
+        p.a = level_args(j);
+        p.E0 = E0;
+        p.EA = EA;
+        p.EB = EB;
+        p.first_level = j;
+        p.last_level = L.Lmax;
+        p.jump_rounds = kPersistJumpRounds;
+        for (int k = 0; k <= kMaxLevels; ++k) {
+            p.capE[k] = k < (int)L.capE.size() ? (int32_t)L.capE[k] : 0;
+            p.capV[k] = k < (int)L.capV.size() ? (int32_t)L.capV[k] : 0;
+        }
+        st.persistent = 1;
+        return launch_levels(p, cu_count(dev), s);
+    };
+    const int64_t persist_max = tune.persist_max_edges;
     st.sync_free = sync_free ? 1 : 0;
     if (!sync_free) {
         // Host-driven: exact grids, pointer jumping relaunched until it converges.
@@ -444,8 +499,12 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             LevelArgs a = level_args(j);
             a.cap_m = (int32_t)m;
             a.cap_n = (int32_t)n;
-            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 28.0 : 12.0) * m + 8.0 * n,
-                     launch_min_incident(l0, a, s));
+            // Deeper levels get their minima from the previous level's compaction.
+            if (l0) PD_TIMED(PK_MIN_INC, 28.0 * m + 8.0 * n, launch_min_incident(a, s));
+            if (m <= persist_max) {
+                PD_TIMED(PK_LEVELS, 60.0 * m, persistent_from(j));
+                break;
+            }
             PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 28.0 : 24.0) * n, launch_own(l0, a, s));
             PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 21.0 * m, launch_classify(a, s));
             for (int round = 0;; ++round) {
@@ -461,7 +520,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
             if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
                 return PANDORA_ERR_NOT_A_TREE;
-            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 40.0 * m_next, launch_compact(a, s));
+            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 56.0 * m_next, launch_compact(a, s));
             n = n_next;
             m = m_next;
             ++j;
@@ -475,7 +534,11 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             const bool l0 = j == 0;
             LevelArgs a = level_args(j);
             const double mj = (double)L.capE[j], nj = (double)L.capV[j];
-            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, 12.0 * mj, launch_min_incident(l0, a, s));
+            if (l0) PD_TIMED(PK_MIN_INC, 12.0 * mj, launch_min_incident(a, s));
+            if (L.capE[j] <= persist_max) {
+                PD_TIMED(PK_LEVELS, 60.0 * mj, persistent_from(j));
+                break;
+            }
             PD_TIMED(l0 ? PK_OWN : PK_OWN_N, 24.0 * nj, launch_own(l0, a, s));
             PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 21.0 * mj, launch_classify(a, s));
             for (int round = 0; round < kSyncFreeJumpRounds; ++round) {
@@ -484,7 +547,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
                 PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, 24.0 * nj, launch_jump(a, s));
                 ++st.jump_launches;
             }
-            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 14.0 * mj, launch_compact(a, s));
+            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 22.0 * mj, launch_compact(a, s));
         }
     }
 
@@ -599,7 +662,11 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     int rc = ensure(ws, L.total, host_bytes_for(B));
     if (rc != PANDORA_OK) return rc;
     const Scratch sc{ws.dev, ws.host};
-    rc = enqueue(sc, L, tune, M <= (int64_t)tune.sync_free_max_edges, voff, B, u, v, w, edge_parent,
+    // this call waits for its stream before returning, so the pinned block's
+    // staging area is free again by the next call
+    int64_t* hv = reinterpret_cast<int64_t*>(static_cast<char*>(ws.host) + sizeof(Control));
+    std::memcpy(hv, voff, sizeof(int64_t) * (B + 1));
+    rc = enqueue(sc, L, tune, M <= (int64_t)tune.sync_free_max_edges, hv, B, u, v, w, edge_parent,
                  vertex_parent, s, st);
     if (rc != PANDORA_OK) return rc;
     rc = finish(sc, L, B, s, st);
@@ -614,6 +681,87 @@ int run_and_drain(const int64_t* voff, int32_t B, const int32_t* u, const int32_
         (void)hipStreamSynchronize(s);
         drain_profile();
     }
+    return rc;
+}
+
+// ---- stream-ordered calls -----------------------------------------------------------
+
+int ensure_sticky(Workspace& ws, hipStream_t s) {
+    if (ws.sticky) return PANDORA_OK;
+    void* p = nullptr;
+    if (hipMalloc(&p, kAlign) != hipSuccess) {
+        (void)hipGetLastError();
+        return PANDORA_ERR_OUT_OF_MEMORY;
+    }
+    ws.sticky = static_cast<uint32_t*>(p);
+    PD_TRY(launch_clear_words(ws.sticky, 1, s));
+    return PANDORA_OK;
+}
+
+// Copies voff into the next staging slot (waiting, if that slot's previous
+// copy has not run yet).
+int stage_voff(Workspace& ws, const int64_t* voff, int32_t B, const int64_t** staged, int* slot) {
+    const size_t need = sizeof(int64_t) * (B + 1);
+    StageSlot& sl = ws.stage[ws.next_stage];
+    if (sl.pending) {
+        if (hipEventSynchronize(sl.done) != hipSuccess) return PANDORA_ERR_HIP;
+        sl.pending = false;
+    }
+    if (!sl.done && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+        sl.done = nullptr;
+        return PANDORA_ERR_HIP;
+    }
+    if (sl.bytes < need) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        sl.host = nullptr;
+        sl.bytes = 0;
+        if (hipHostMalloc(&sl.host, need, hipHostMallocDefault) != hipSuccess) {
+            sl.host = nullptr;
+            (void)hipGetLastError();
+            return PANDORA_ERR_OUT_OF_MEMORY;
+        }
+        sl.bytes = need;
+    }
+    std::memcpy(sl.host, voff, need);
+    *staged = static_cast<const int64_t*>(sl.host);
+    *slot = ws.next_stage;
+    ws.next_stage = (ws.next_stage + 1) % kStageSlots;
+    return PANDORA_OK;
+}
+
+// The whole path enqueued on s with no host round trip (the sync-free level
+// loop); input errors land in the stream's sticky status word.
+int run_async(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, const float* w,
+              int32_t* edge_parent, int32_t* vertex_parent, hipStream_t s) {
+    const int64_t N = voff[B];
+    const int64_t M = N - B;
+    int dev = 0;
+    PD_TRY(hipGetDevice(&dev));
+    Workspace& ws = *workspace_for(dev, s);
+    std::lock_guard<std::mutex> lock(ws.mu);
+    if (M == 0) {   // only single-vertex trees: every vertex is a root
+        PD_TRY(launch_fill_i32(vertex_parent, N, -1, s));
+        return PANDORA_OK;
+    }
+    const pandora_tuning_t tune = current_tuning();
+    const Layout L = make_layout(N, B, tune.chain_digit_bits, tune.sort_tile_cfg);
+    int rc = ensure(ws, L.total, host_bytes_for(1));
+    if (rc == PANDORA_OK) rc = ensure_sticky(ws, s);
+    if (rc != PANDORA_OK) return rc;
+    const int64_t* staged = nullptr;
+    int slot = -1;
+    if (B > 1) {
+        rc = stage_voff(ws, voff, B, &staged, &slot);
+        if (rc != PANDORA_OK) return rc;
+    }
+    Stats st;
+    const Scratch sc{ws.dev, ws.host};
+    t_capturing = true;   // no profiler events: nothing would wait for them
+    rc = enqueue(sc, L, tune, true, staged, B, u, v, w, edge_parent, vertex_parent, s, st);
+    t_capturing = false;
+    if (rc == PANDORA_OK && launch_finalize(at<Control>(ws.dev, L.ctrl), B, ws.sticky, s) != hipSuccess)
+        rc = PANDORA_ERR_HIP;
+    if (slot >= 0 && hipEventRecord(ws.stage[slot].done, s) == hipSuccess) ws.stage[slot].pending = true;
     return rc;
 }
 
@@ -643,18 +791,76 @@ int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u,
     return run_and_drain(voff, B, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
 }
 
+int pandora_dendrogram_async(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                             int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream) {
+    if (n < 1 || n > INT32_MAX || !vertex_parent) return PANDORA_ERR_INVALID_ARG;
+    if (n > 1 && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    const int64_t voff[2] = {0, n};
+    return run_async(voff, 1, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
+}
+
+int pandora_dendrogram_batched_async(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,
+                                     const float* w, int32_t* edge_parent, int32_t* vertex_parent,
+                                     void* hip_stream) {
+    if (B < 1 || !voff || !vertex_parent || voff[0] != 0) return PANDORA_ERR_INVALID_ARG;
+    for (int32_t b = 0; b < B; ++b)
+        if (voff[b + 1] <= voff[b]) return PANDORA_ERR_INVALID_ARG;
+    if (voff[B] > INT32_MAX) return PANDORA_ERR_INVALID_ARG;
+    if (voff[B] > B && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    return run_async(voff, B, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
+}
+
+int pandora_stream_status(void* hip_stream) {
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PANDORA_ERR_HIP;
+    Workspace& ws = *workspace_for(dev, s);
+    std::lock_guard<std::mutex> lock(ws.mu);
+    if (hipStreamSynchronize(s) != hipSuccess) return PANDORA_ERR_HIP;
+    if (!ws.sticky) return PANDORA_OK;
+    uint32_t e = 0;
+    if (hipMemcpyAsync(&e, ws.sticky, sizeof(e), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return PANDORA_ERR_HIP;
+    if (e == 0) return PANDORA_OK;
+    if (launch_clear_words(ws.sticky, 1, s) != hipSuccess) return PANDORA_ERR_HIP;
+    return status_from_err(e);
+}
+
+int pandora_set_workspace(void* hip_stream, void* dev_ptr, size_t bytes) {
+    if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign != 0 || bytes == 0))
+        return PANDORA_ERR_INVALID_ARG;
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PANDORA_ERR_HIP;
+    Workspace& ws = *workspace_for(dev, s);
+    std::lock_guard<std::mutex> lock(ws.mu);
+    // earlier calls on the stream may still use the current buffer
+    if (hipStreamSynchronize(s) != hipSuccess) return PANDORA_ERR_HIP;
+    if (ws.owned && ws.dev) (void)hipFree(ws.dev);
+    ws.dev = dev_ptr;
+    ws.bytes = dev_ptr ? bytes : 0;
+    ws.owned = dev_ptr == nullptr;
+    return PANDORA_OK;
+}
+
 size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B) {
     if (B < 1 || n_total_vertices < B || n_total_vertices > INT32_MAX) return 0;
     if (n_total_vertices == B) return 0;
-    return make_layout(n_total_vertices, B).total;
+    // enough for every tuning: the radix tile and digit width change the size
+    // of the look-back buffers
+    size_t most = 0;
+    for (int cfg = 0; cfg < kNumSortCfg; ++cfg)
+        for (int bits : {8, 9}) most = std::max(most, make_layout(n_total_vertices, B, bits, cfg).total);
+    return most;
 }
 
 int pandora_last_stats(int64_t* out, int cap) {
-    const int64_t vals[6] = {g_last.levels, g_last.sum_edges, g_last.jump_launches, g_last.tail_levels,
-                             g_last.tail_entry_edges, g_last.sync_free};
+    const int64_t vals[7] = {g_last.levels, g_last.sum_edges, g_last.jump_launches, g_last.tail_levels,
+                             g_last.tail_entry_edges, g_last.sync_free, g_last.persistent};
     if (!out || cap < 0) return -PANDORA_ERR_INVALID_ARG;
     int k = 0;
-    for (; k < cap && k < 6; ++k) out[k] = vals[k];
+    for (; k < cap && k < 7; ++k) out[k] = vals[k];
     return k;
 }
 
@@ -768,7 +974,9 @@ static int graph_create(int32_t B, const int64_t* voff, const int32_t* u, const 
             if (launch_fill_i32(vertex_parent, N, -1, cs) != hipSuccess) rc = PANDORA_ERR_HIP;
         } else {
             const Scratch sc{g->dev, g->host};
-            rc = enqueue(sc, g->L, tune, true, voff, B, u, v, w, edge_parent, vertex_parent, cs, st);
+            int64_t* hv = reinterpret_cast<int64_t*>(static_cast<char*>(g->host) + sizeof(Control));
+            std::memcpy(hv, voff, sizeof(int64_t) * (B + 1));
+            rc = enqueue(sc, g->L, tune, true, hv, B, u, v, w, edge_parent, vertex_parent, cs, st);
         }
         t_capturing = false;
         if (hipStreamEndCapture(cs, &g->graph) != hipSuccess && rc == PANDORA_OK) rc = PANDORA_ERR_HIP;
@@ -827,13 +1035,18 @@ void pandora_release_workspaces(void) {
     for (auto& kv : g_ws) {
         Workspace& ws = *kv.second;
         std::lock_guard<std::mutex> l(ws.mu);
-        if (ws.dev) {
-            (void)hipStreamSynchronize(ws.stream);
-            (void)hipFree(ws.dev);
-        }
+        (void)hipStreamSynchronize(ws.stream);
+        if (ws.dev && ws.owned) (void)hipFree(ws.dev);
         if (ws.host) (void)hipHostFree(ws.host);
+        if (ws.sticky) (void)hipFree(ws.sticky);
+        for (StageSlot& sl : ws.stage) {
+            if (sl.host) (void)hipHostFree(sl.host);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            sl = StageSlot{};
+        }
         ws.dev = nullptr;
         ws.host = nullptr;
+        ws.sticky = nullptr;
         ws.bytes = ws.host_bytes = 0;
     }
     g_ws.clear();

@@ -20,7 +20,8 @@ OK, INVALID_ARG = 0, 1
 
 class Tuning(ctypes.Structure):
     _fields_ = [("sync_free_max_edges", ctypes.c_int32), ("jump_steps", ctypes.c_int32),
-                ("chain_digit_bits", ctypes.c_int32), ("sort_tile_cfg", ctypes.c_int32)]
+                ("chain_digit_bits", ctypes.c_int32), ("sort_tile_cfg", ctypes.c_int32),
+                ("persist_max_edges", ctypes.c_int32)]
 
 
 @pytest.fixture(scope="module")
@@ -39,6 +40,9 @@ def lib():
     L.pandora_graph_create_batched.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 7
     L.pandora_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     L.pandora_last_stats.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.pandora_dendrogram_async.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 6
+    L.pandora_dendrogram_batched_async.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 7
+    L.pandora_set_workspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     yield L
     L.pandora_set_thread_tuning(None)
 
@@ -53,7 +57,10 @@ def test_header_declares_the_api():
     for must in ("pandora_dendrogram", "pandora_dendrogram_batched", "pandora_workspace_bytes",
                  "pandora_graph_create", "pandora_graph_launch", "pandora_set_tuning"):
         assert must in names
-    assert len(names) == 16
+    for must in ("pandora_dendrogram_async", "pandora_dendrogram_batched_async", "pandora_stream_status",
+                 "pandora_set_workspace"):
+        assert must in names
+    assert len(names) == 20
 
 
 def test_library_exports_exactly_the_declared_functions(lib):
@@ -103,6 +110,14 @@ def test_argument_errors_come_back_before_any_launch(lib):
     assert lib.pandora_graph_launch(None, None) == INVALID_ARG
     lib.pandora_graph_destroy(None)   # a no-op
     assert lib.pandora_last_stats(None, 6) == -INVALID_ARG
+    # the stream-ordered variants validate the same way, before touching the device
+    assert lib.pandora_dendrogram_async(0, d, d, d, d, d, None) == INVALID_ARG
+    assert lib.pandora_dendrogram_async(10, d, None, d, d, d, None) == INVALID_ARG
+    assert lib.pandora_dendrogram_batched_async(2, voff(0, 4, 2), d, d, d, d, d, None) == INVALID_ARG
+    assert lib.pandora_dendrogram_batched_async(2, voff(0, 3, 5), d, d, d, None, d, None) == INVALID_ARG
+    # caller scratch must be 256-byte aligned and non-empty
+    assert lib.pandora_set_workspace(None, ctypes.c_void_p(4096 + 8), 1 << 20) == INVALID_ARG
+    assert lib.pandora_set_workspace(None, ctypes.c_void_p(4096), 0) == INVALID_ARG
 
 
 def test_tuning_validation_and_thread_scope(lib):
@@ -110,17 +125,18 @@ def test_tuning_validation_and_thread_scope(lib):
     assert lib.pandora_get_tuning(ctypes.byref(old)) == OK
     try:
         for bad in (dict(jump_steps=0), dict(jump_steps=5000), dict(chain_digit_bits=7),
-                    dict(sort_tile_cfg=4), dict(sort_tile_cfg=-1), dict(sync_free_max_edges=-1)):
-            t = Tuning(0, 16, 0, 3)
+                    dict(sort_tile_cfg=4), dict(sort_tile_cfg=-1), dict(sync_free_max_edges=-1),
+                    dict(persist_max_edges=-1)):
+            t = Tuning(0, 16, 0, 3, 0)
             for k, v in bad.items():
                 setattr(t, k, v)
             assert lib.pandora_set_tuning(ctypes.byref(t)) == INVALID_ARG, bad
             assert lib.pandora_set_thread_tuning(ctypes.byref(t)) == INVALID_ARG, bad
         assert lib.pandora_set_tuning(None) == INVALID_ARG
 
-        glob = Tuning(1000, 8, 9, 1)
+        glob = Tuning(1000, 8, 9, 1, 5000)
         assert lib.pandora_set_tuning(ctypes.byref(glob)) == OK
-        mine = Tuning(0, 32, 8, 2)
+        mine = Tuning(0, 32, 8, 2, 0)
         assert lib.pandora_set_thread_tuning(ctypes.byref(mine)) == OK
         got = Tuning()
         lib.pandora_get_tuning(ctypes.byref(got))
@@ -131,11 +147,12 @@ def test_tuning_validation_and_thread_scope(lib):
         def other():
             t = Tuning()
             lib.pandora_get_tuning(ctypes.byref(t))
-            seen["t"] = (t.sync_free_max_edges, t.jump_steps, t.chain_digit_bits, t.sort_tile_cfg)
+            seen["t"] = (t.sync_free_max_edges, t.jump_steps, t.chain_digit_bits, t.sort_tile_cfg,
+                         t.persist_max_edges)
         th = threading.Thread(target=other)
         th.start()
         th.join()
-        assert seen["t"] == (1000, 8, 9, 1)       # another thread sees the process-wide knobs
+        assert seen["t"] == (1000, 8, 9, 1, 5000)       # another thread sees the process-wide knobs
 
         assert lib.pandora_set_thread_tuning(None) == OK
         lib.pandora_get_tuning(ctypes.byref(got))
@@ -177,7 +194,7 @@ def test_explicit_tuning_turns_the_table_off():
     import paper_2401_06089_amd as pd
     from paper_2401_06089_amd import autotune
     table = {"arch": None, "buckets": [{"max_edges": 2**31 - 1, "tuning": dict(
-        sync_free_max_edges=0, jump_steps=4, chain_digit_bits=8, sort_tile_cfg=0)}]}
+        sync_free_max_edges=0, jump_steps=4, chain_digit_bits=8, sort_tile_cfg=0, persist_max_edges=0)}]}
     old = pd.get_tuning()
     try:
         autotune.install(table)

@@ -11,10 +11,18 @@ from gpu_util import assert_matches_oracle
 pytestmark = pytest.mark.gpu
 
 MODES = {
-    "synced": dict(sync_free_max_edges=0, jump_steps=16, chain_digit_bits=0),
-    "syncfree": dict(sync_free_max_edges=2**31 - 1, jump_steps=16, chain_digit_bits=0),
-    "syncfree_short_jumps_9bit": dict(sync_free_max_edges=2**31 - 1, jump_steps=2, chain_digit_bits=9),
-    "synced_9bit": dict(sync_free_max_edges=0, jump_steps=4, chain_digit_bits=9),
+    "synced": dict(sync_free_max_edges=0, jump_steps=16, chain_digit_bits=0, persist_max_edges=0),
+    "syncfree": dict(sync_free_max_edges=2**31 - 1, jump_steps=16, chain_digit_bits=0, persist_max_edges=0),
+    "syncfree_short_jumps_9bit": dict(sync_free_max_edges=2**31 - 1, jump_steps=2, chain_digit_bits=9,
+                                      persist_max_edges=0),
+    "synced_9bit": dict(sync_free_max_edges=0, jump_steps=4, chain_digit_bits=9, persist_max_edges=0),
+    # every level in the persistent kernel, level 0 included
+    "synced_persist_all": dict(sync_free_max_edges=0, jump_steps=16, chain_digit_bits=0,
+                               persist_max_edges=2**31 - 1),
+    "syncfree_persist_short_jumps": dict(sync_free_max_edges=2**31 - 1, jump_steps=1, chain_digit_bits=0,
+                                         persist_max_edges=2**31 - 1),
+    "synced_persist_mid": dict(sync_free_max_edges=0, jump_steps=16, chain_digit_bits=0,
+                               persist_max_edges=1 << 15),
 }
 
 
@@ -41,7 +49,12 @@ def test_modes_parity(maker, mode):
     t = maker()
     assert_matches_oracle(t, mode)
     import paper_2401_06089_amd as pd
-    assert pd.last_stats()["sync_free"] == (1 if "syncfree" in mode else 0)
+    st = pd.last_stats()
+    assert st["sync_free"] == (1 if "syncfree" in mode else 0)
+    if "persist_all" in mode or "persist_short" in mode:
+        assert st["persistent"] == 1          # every tree here is larger than the LDS tail
+    if "persist" not in mode:
+        assert st["persistent"] == 0
 
 
 def test_modes_forest(mode):
