@@ -156,9 +156,10 @@ PANDORA_API int pandora_last_stats(int64_t* out, int cap);
  *   sort_tile_cfg        radix tile: 0..3 = 1024, 2048, 4096, 8192 keys per
  *                        workgroup [3]
  *   persist_max_edges    levels with at most this many edges run in one
- *                        persistent launch (one workgroup per compute unit,
- *                        grid barriers between the steps of a level) instead
- *                        of one launch per step; 0 turns it off [262144]
+ *                        persistent launch (workgroups on a quarter of the
+ *                        compute units, grid barriers between the steps of a
+ *                        level) instead of one launch per step; 0 turns it
+ *                        off [0: on gfx950 the per-step launches are faster]
  * pandora_set_tuning returns INVALID_ARG for out-of-range values.
  * pandora_set_thread_tuning overrides them for calls made by the calling
  * thread only (NULL removes the override), so concurrent callers can tune

@@ -35,7 +35,7 @@ KNOBS = {
     "jump_steps": [4, 8, 16, 32],
     "chain_digit_bits": [8, 9],
     "sync_free_max_edges": [0, 2**31 - 1],
-    "persist_max_edges": [0, 1 << 16, 1 << 18, 1 << 20],
+    "persist_max_edges": [0, 1 << 16, 1 << 18],
 }
 
 DEFAULT_SIZES = [1_000, 10_000, 100_000, 1_000_000, 10_000_000]
@@ -64,6 +64,10 @@ def _device_trees(n: int, seed: int, device) -> list:
 
 
 def _time_setting(trees, tuning: dict, reps: int) -> float:
+    # an installed table would replace the candidate on every call: suspend it
+    import paper_2401_06089_amd as pkg
+    hook = pkg._tuning_hook
+    pkg._set_tuning_hook(None)
     set_thread_tuning(tuning)
     try:
         outs = [(torch.empty(t[0] - 1, dtype=torch.int32, device=t[1].device),
@@ -83,6 +87,7 @@ def _time_setting(trees, tuning: dict, reps: int) -> float:
         return statistics.median(times) * 1e3
     finally:
         set_thread_tuning(None)
+        pkg._set_tuning_hook(hook)
 
 
 def tune_size(n: int, seed: int = 0, rounds: int = 2, reps: Optional[int] = None, log=print) -> dict:
@@ -109,6 +114,8 @@ def tune_size(n: int, seed: int = 0, rounds: int = 2, reps: Optional[int] = None
 
 
 def build_table(sizes: List[int] = DEFAULT_SIZES, seed: int = 0, log=print) -> dict:
+    # an installed table would override every candidate: tune without one
+    install(None)
     results = [tune_size(n, seed, log=log) for n in sizes]
     buckets = []
     for k, r in enumerate(results):

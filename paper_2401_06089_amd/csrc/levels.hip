@@ -459,8 +459,8 @@ __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
 
 // ---- persistent kernel: all mid-size levels in one launch -------------------------
 //
-// One workgroup per CU walks through the levels; grid barriers separate the
-// steps.  Every decision that shapes the loop (a level's size, whether pointer
+// A fixed grid of workgroups walks through the levels; grid barriers separate
+// the steps.  Every decision that shapes the loop (a level's size, whether pointer
 // jumping converged) is read after a barrier from words written before it, so
 // all workgroups take the same path.  Barrier waits are bounded and stop once
 // an input error is flagged (then every step returns at once and the outputs

@@ -45,7 +45,7 @@ pandora_tuning_t g_tune = {
     /*jump_steps=*/16,
     /*chain_digit_bits=*/0,
     /*sort_tile_cfg=*/kDefaultSortCfg,
-    /*persist_max_edges=*/1 << 18,
+    /*persist_max_edges=*/0,
 };
 
 thread_local bool t_has_tune = false;
@@ -63,8 +63,8 @@ bool tuning_valid(const pandora_tuning_t* t) {
            t->sort_tile_cfg >= 0 && t->sort_tile_cfg < kNumSortCfg && t->persist_max_edges >= 0;
 }
 
-// Compute units of a device (the persistent level kernel runs one workgroup
-// on each).
+// Compute units of a device (the persistent level kernel sizes its grid by
+// them).
 int cu_count(int dev) {
     static std::mutex mu;
     static std::map<int, int> cache;
@@ -485,7 +485,9 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             p.capV[k] = k < (int)L.capV.size() ? (int32_t)L.capV[k] : 0;
         }
         st.persistent = 1;
-        return launch_levels(p, cu_count(dev), s);
+        // a quarter of the CUs: fewer arrivals per grid barrier, enough
+        // workgroups for levels of this size (measured best of 1/1 to 1/8)
+        return launch_levels(p, std::max(1, cu_count(dev) / 4), s);
     };
     const int64_t persist_max = tune.persist_max_edges;
     st.sync_free = sync_free ? 1 : 0;
