@@ -22,6 +22,7 @@ import math
 import os
 import statistics
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -147,6 +148,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="c5: admission budget")
     ap.add_argument("--max-batch-edges", type=int, default=64 << 20, help="c5: edge cap of one batch")
     ap.add_argument("--policy", default="fifo", choices=["fifo", "small_first"], help="c5: batching order")
+    ap.add_argument("--sample-every", type=int, default=4,
+                    help="bracket the dominant kernel with HIP events on every k-th timed step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy: a kernel of known traffic "
                          "for scaling hardware byte counters")
@@ -237,23 +240,32 @@ def main():
     dominant = max(stages, key=lambda k: stages[k]["ms"])
     dom_kind = stages[dominant]["kind"]
 
-    # Timed region: only the dominant kernel is bracketed with HIP events.
-    pd.profile_enable(1 << dom_kind)
+    # Timed region: the dominant kernel is bracketed with HIP events on every
+    # args.sample_every-th step (a pair of events per launch costs a few
+    # microseconds, which matters for small trees with many launches).
     lat = []
+    dom = {"ms": 0.0, "bytes": 0.0, "launches": 0}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        sample = not graphs and i % args.sample_every == 0
+        pd.profile_enable((1 << dom_kind) if sample else 0)
         a = time.perf_counter()
         step()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - a)
+        if sample:
+            d = pd.profile_read()[dominant]
+            for k in dom:
+                dom[k] += d[k]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     if graphs:
+        pd.profile_enable(1 << dom_kind)
         for _ in range(args.steps):
             prof_step()
         torch.cuda.synchronize()
-    dom = pd.profile_read()[dominant]
+        dom = pd.profile_read()[dominant]
     pd.profile_enable(0)
 
     ms_per_step = 1000.0 * elapsed / args.steps
@@ -288,7 +300,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_s * 1000,
                      "launches": dom["launches"],
-                     "measured_on": "eager calls after the timed graph replays" if graphs else "timed steps"},
+                     "measured_on": ("eager calls after the timed graph replays" if graphs
+                                     else f"every {args.sample_every}th timed step")},
         "path_hbm": {"algorithmic_bytes_per_step": sum(s["bytes"] for s in stages.values()),
                      "algorithmic_GBps": sum(s["bytes"] for s in stages.values()) / (ms_per_step / 1000) / 1e9},
     }
@@ -397,6 +410,8 @@ def run_serving(args, dev):
         t = gen.rrt(int(n), gen.hash2(5, i), weights="lognormal")
         pool.append((t.n, torch.from_numpy(t.u).to(dev), torch.from_numpy(t.v).to(dev),
                      torch.from_numpy(t.w).to(dev)))
+        if i % 64 == 63:
+            log(f"pool: {i + 1}/{len(sizes)} trees")
     torch.cuda.synchronize()
     log(f"pool of {len(pool)} trees ({int(sizes.sum() - len(sizes))} edges) in {time.time() - t0:.1f}s")
 
@@ -417,6 +432,22 @@ def run_serving(args, dev):
         r.future.result()
     srv.done.clear()
 
+    # The client consumes each result as it completes (here: checks it and
+    # drops it), so device memory holds only what is in flight.
+    done_cv = threading.Condition()
+    done = {"n": 0, "failed": []}
+
+    def consumed(r):
+        def cb(f):
+            exc = f.exception()
+            r.future = None
+            with done_cv:
+                if exc is not None:
+                    done["failed"].append((r.rid, repr(exc)))
+                done["n"] += 1
+                done_cv.notify_all()
+        return cb
+
     start = time.perf_counter()
     reqs = []
     for i, off in enumerate(offsets):
@@ -427,10 +458,14 @@ def run_serving(args, dev):
         n, u, v, w = pool[int(picks[i])]
         r = Request(i, n, u, v, w, arrival=due)
         reqs.append(r)
-        srv.submit(r)
-    for r in reqs:
-        r.future.result()
+        fut = srv.submit(r)
+        fut.add_done_callback(consumed(r))
+    with done_cv:
+        while done["n"] < len(reqs):
+            done_cv.wait(timeout=1.0)
     end = time.perf_counter()
+    if done["failed"]:
+        raise RuntimeError(f"{len(done['failed'])} requests failed, first: {done['failed'][0]}")
     srv.close()
     kept = [r for r in reqs if r.arrival - start >= args.discard]
     span = max(r.finished for r in kept) - min(r.arrival for r in kept) if kept else 1.0

@@ -127,7 +127,7 @@ __host__ __device__ inline bool tail_level(int64_t m, int64_t n, int tail_e, int
     return m == 0 || (m <= tail_e && n <= tail_v);
 }
 
-hipError_t launch_min_incident(const LevelArgs& a, hipStream_t s);
+hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s);
 
 // Levels [first_level, last_level) in one persistent launch (stops at the
 // first level small enough for the LDS tail).  a holds the pointers shared by

@@ -7,13 +7,11 @@
 // levels in compaction order.  Every comparison uses ranks, never positions.
 //
 // One level, m_j edges and n_j vertices:
-//   k_min_incident  (level 0) min64[x] = min over incident edges of
-//                   (rank << 32 | pos): the lightest incident edge (Eq.
-//                   vertexparent) and where its record lives.  It also builds
-//                   the 16-byte edge records from the caller's arrays,
-//                   translating the tree-local ids of a forest and validating
-//                   them.  Deeper levels get the same minima from the
-//                   compaction that writes their edges.
+//   k_min_incident  min64[x] = min over incident edges of (rank << 32 | pos):
+//                   the lightest incident edge (Eq. vertexparent) and where
+//                   its record lives.  At level 0 it also builds the 16-byte
+//                   edge records from the caller's arrays, translating the
+//                   tree-local ids of a forest and validating them.
 //   k_own           per vertex: one gather of its lightest edge's record gives
 //                   the hook ptr[x] = other endpoint, the rank table entry and
 //                   (level 0) the vertex's dendrogram parent; the vertex marks
@@ -29,8 +27,7 @@
 //                   host relaunches until every vertex has its label); each
 //                   vertex writes its flat label and records its lightest
 //                   edge's supervertex for the expansion.
-//   k_compact       stable compaction of alpha edges, endpoints relabelled;
-//                   each written edge also bids for the next level's minima.
+//   k_compact       stable compaction of alpha edges, endpoints relabelled.
 //
 // Vertices of all levels share one flat id space: level j occupies
 // [off_j, off_j + n_j).  Isolated vertices (finished components of a forest)
@@ -120,6 +117,7 @@ __device__ uint64_t wave_lookback(const uint64_t* lb, int64_t tile, Control* ctr
 
 // After an input error every level kernel returns at once: the call's outputs
 // are unspecified then, and nothing may index with the damaged tables.
+template <bool L0>
 __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
     const LevelView L = level_view(a);
     if (L.skip || a.ctrl->err) return;
@@ -130,22 +128,26 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
         a.ctrl->not_converged = 0;
     }
     if (i >= L.m) return;
-    const int32_t b = a.forest.tree_of_edge(i);
-    const int64_t v0 = a.forest.voff[b];
-    const int64_t nb = a.forest.voff[b + 1] - v0;
-    int64_t x = a.in_u[i];
-    int64_t y = a.in_v[i];
-    if (x < 0 || x >= nb || y < 0 || y >= nb) {
-        raise_err(a.ctrl, kErrBadVertex);
-        x = (x < 0 || x >= nb) ? 0 : x;
-        y = (y < 0 || y >= nb) ? 0 : y;
-    }
     EdgeRec e;
-    e.u = (int32_t)(v0 + x);
-    e.v = (int32_t)(v0 + y);
-    e.r = a.rank[i];
-    e.id = (int32_t)i;
-    a.E[i] = e;
+    if (L0) {
+        const int32_t b = a.forest.tree_of_edge(i);
+        const int64_t v0 = a.forest.voff[b];
+        const int64_t nb = a.forest.voff[b + 1] - v0;
+        int64_t x = a.in_u[i];
+        int64_t y = a.in_v[i];
+        if (x < 0 || x >= nb || y < 0 || y >= nb) {
+            raise_err(a.ctrl, kErrBadVertex);
+            x = (x < 0 || x >= nb) ? 0 : x;
+            y = (y < 0 || y >= nb) ? 0 : y;
+        }
+        e.u = (int32_t)(v0 + x);
+        e.v = (int32_t)(v0 + y);
+        e.r = a.rank[i];
+        e.id = (int32_t)i;
+        a.E[i] = e;
+    } else {
+        e = a.E[i];
+    }
     const uint64_t key = ((uint64_t)(uint32_t)e.r << 32) | (uint64_t)(uint32_t)i;
     // Read first: values only decrease, so a stale read can only cause a
     // redundant atomic, never a missed one.
@@ -341,8 +343,11 @@ __device__ __forceinline__ void compact_prepare(const LevelArgs& a, const NextSi
     }
 }
 
-// One tile of the stable alpha compaction (whole workgroup).
-template <bool L0>
+// One tile of the stable alpha compaction (whole workgroup).  With BID each
+// written edge also bids for the next level's minima (the persistent kernel
+// saves a grid barrier that way; with one launch per step a separate
+// k_min_incident is faster, measured).
+template <bool L0, bool BID>
 __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView& L, const NextSizes& nx,
                                              int64_t tile) {
     constexpr int W = kScanBlock / kWave;
@@ -392,12 +397,13 @@ __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView
             o.r = e.r;
             o.id = 0;
             a.out[pos] = o;
-            // The next level's lightest incident edges (its min64 words were
-            // reset by this level's pointer jumping): read first, values only
-            // decrease.
-            const uint64_t key = ((uint64_t)(uint32_t)e.r << 32) | (uint64_t)pos;
-            if (a.min64[ux] > key) atomicMin((unsigned long long*)&a.min64[ux], (unsigned long long)key);
-            if (a.min64[vx] > key) atomicMin((unsigned long long*)&a.min64[vx], (unsigned long long)key);
+            if (BID) {
+                // the next level's lightest incident edges (its min64 words
+                // were reset by this level's pointer jumping)
+                const uint64_t key = ((uint64_t)(uint32_t)e.r << 32) | (uint64_t)pos;
+                if (a.min64[ux] > key) atomicMin((unsigned long long*)&a.min64[ux], (unsigned long long)key);
+                if (a.min64[vx] > key) atomicMin((unsigned long long*)&a.min64[vx], (unsigned long long)key);
+            }
         } else {
             overflow = true;
         }
@@ -454,7 +460,7 @@ __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
     compact_prepare(a, nx, (int64_t)blockIdx.x * kScanBlock + threadIdx.x);
     const int64_t tile = blockIdx.x;
     if (tile >= scan_tiles(L.m)) return;
-    compact_tile<L0>(a, L, nx, tile);
+    compact_tile<L0, false>(a, L, nx, tile);
 }
 
 // ---- persistent kernel: all mid-size levels in one launch -------------------------
@@ -539,7 +545,7 @@ __device__ void persistent_level(const LevelArgs& a, const LevelView& L, int jum
     __syncthreads();
     if (*s_tile == 0) {
         for (int64_t g = gtid; g < scan_tiles(nx.m) || g == 0; g += gsize) compact_prepare(a, nx, g);
-        for (int64_t t = blockIdx.x; t < scan_tiles(L.m); t += gridDim.x) compact_tile<L0>(a, L, nx, t);
+        for (int64_t t = blockIdx.x; t < scan_tiles(L.m); t += gridDim.x) compact_tile<L0, true>(a, L, nx, t);
     }
     grid_barrier(c, bar);
 }
@@ -786,9 +792,10 @@ inline unsigned blocks_for(int64_t n, int per) {
 
 }  // namespace
 
-hipError_t launch_min_incident(const LevelArgs& a, hipStream_t s) {
+hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s) {
     const int64_t work = a.cap_m > scan_tiles(a.cap_m) ? a.cap_m : scan_tiles(a.cap_m);
-    k_min_incident<<<blocks_for(work, 256), 256, 0, s>>>(a);
+    if (level0) k_min_incident<true><<<blocks_for(work, 256), 256, 0, s>>>(a);
+    else k_min_incident<false><<<blocks_for(work, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

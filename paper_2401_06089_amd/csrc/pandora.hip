@@ -209,14 +209,14 @@ thread_local Stats g_last;
 enum ProfKind {
     PK_ZERO, PK_SORT_HIST, PK_SORT_W_FIRST, PK_SORT_W_MID, PK_SORT_W_LAST, PK_MIN_INC,
     PK_OWN, PK_CLASSIFY, PK_JUMP, PK_COMPACT, PK_TAIL, PK_WALK_HIST, PK_SORT_C_PASS, PK_STITCH,
-    PK_OWN_N, PK_CLASSIFY_N, PK_JUMP_N, PK_COMPACT_N, PK_LEVELS,
+    PK_MIN_INC_N, PK_OWN_N, PK_CLASSIFY_N, PK_JUMP_N, PK_COMPACT_N, PK_LEVELS,
     PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "zero_control", "sort_hist", "sort_pass_weight_first", "sort_pass_weight_mid",
     "sort_pass_weight_last", "min_incident_l0", "own_l0", "classify_l0", "jump_l0", "compact_l0",
-    "tail", "walk_hist", "sort_pass_chain", "stitch", "own_ln", "classify_ln", "jump_ln",
-    "compact_ln", "levels_persistent"};
+    "tail", "walk_hist", "sort_pass_chain", "stitch", "min_incident_ln", "own_ln", "classify_ln",
+    "jump_ln", "compact_ln", "levels_persistent"};
 
 struct Prof {
     std::mutex mu;
@@ -501,8 +501,8 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             LevelArgs a = level_args(j);
             a.cap_m = (int32_t)m;
             a.cap_n = (int32_t)n;
-            // Deeper levels get their minima from the previous level's compaction.
-            if (l0) PD_TIMED(PK_MIN_INC, 28.0 * m + 8.0 * n, launch_min_incident(a, s));
+            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 28.0 : 12.0) * m + 8.0 * n,
+                     launch_min_incident(l0, a, s));
             if (m <= persist_max) {
                 PD_TIMED(PK_LEVELS, 60.0 * m, persistent_from(j));
                 break;
@@ -522,7 +522,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
             if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
                 return PANDORA_ERR_NOT_A_TREE;
-            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 56.0 * m_next, launch_compact(a, s));
+            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 40.0 * m_next, launch_compact(a, s));
             n = n_next;
             m = m_next;
             ++j;
@@ -536,7 +536,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             const bool l0 = j == 0;
             LevelArgs a = level_args(j);
             const double mj = (double)L.capE[j], nj = (double)L.capV[j];
-            if (l0) PD_TIMED(PK_MIN_INC, 12.0 * mj, launch_min_incident(a, s));
+            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, 12.0 * mj, launch_min_incident(l0, a, s));
             if (L.capE[j] <= persist_max) {
                 PD_TIMED(PK_LEVELS, 60.0 * mj, persistent_from(j));
                 break;
@@ -549,7 +549,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
                 PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, 24.0 * nj, launch_jump(a, s));
                 ++st.jump_launches;
             }
-            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 22.0 * mj, launch_compact(a, s));
+            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 14.0 * mj, launch_compact(a, s));
         }
     }
 
