@@ -39,7 +39,10 @@ struct Control {
     uint32_t grid_bar;        // arrivals at the persistent level kernel's grid barriers
     uint32_t sort_tiles[8];   // dynamic tile counters, one per radix pass
     LevelInfo lv[kMaxLevels]; // level sizes (lv[0] set at the start of a call)
-    uint32_t hist[8][512];    // per-pass digit histograms (8- or 9-bit digits)
+    // Per-pass digit histograms (8- or 9-bit digits).  Thousands of
+    // workgroups add into these words at once; their placement in cache lines
+    // measurably changes the histogram kernels' speed, so it is pinned.
+    alignas(256) uint32_t hist[8][512];
 };
 
 // A forest of B trees: tree b owns vertices [voff[b], voff[b+1]) and edges

@@ -23,8 +23,9 @@ namespace pandora {
 namespace {
 
 constexpr int kWalkLimit = 64;
+constexpr int kWalkBlock = 1024;   // threads of a walk workgroup
 
-__global__ __launch_bounds__(256) void k_walk_hist(WalkArgs a) {
+__global__ __launch_bounds__(kWalkBlock) void k_walk_hist(WalkArgs a) {
     __shared__ uint32_t s_h[4][kMaxRadix];
     const int radix = 1 << a.bits;
     const uint32_t mask = (uint32_t)radix - 1u;
@@ -113,10 +114,12 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t value) {
 }  // namespace
 
 hipError_t launch_walk_hist(const WalkArgs& a, hipStream_t s) {
-    int64_t blocks = (a.m + 256 * 8 - 1) / (256 * 8);
+    // Fewer, larger workgroups: each adds its chain-key histogram to the
+    // global one with atomics (512 x 1024 threads still fill the GPU).
+    int64_t blocks = (a.m + kWalkBlock * 8 - 1) / (kWalkBlock * 8);
     if (blocks < 1) blocks = 1;
-    if (blocks > 8192) blocks = 8192;
-    k_walk_hist<<<(unsigned)blocks, 256, 0, s>>>(a);
+    if (blocks > 512) blocks = 512;
+    k_walk_hist<<<(unsigned)blocks, kWalkBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 

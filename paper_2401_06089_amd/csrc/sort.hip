@@ -31,6 +31,7 @@ constexpr uint64_t kFlagMask = 3ull << 62;
 constexpr uint64_t kCountMask = ~kFlagMask;
 constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr int kLookBatch = 4;   // earlier tiles read per look-back hop
+constexpr int kHistBlock = 1024;  // threads of a histogram workgroup
 
 // Waves per SIMD to reserve registers for: the 8192-key, 8-bit pass needs
 // 52 KB of LDS, so three 512-thread workgroups fit on a CU if each wave keeps
@@ -57,7 +58,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wsum
 }
 
 template <int SRC>
-__global__ __launch_bounds__(256) void k_sort_hist(SortHistArgs a) {
+__global__ __launch_bounds__(kHistBlock) void k_sort_hist(SortHistArgs a) {
     __shared__ uint32_t s_h[4][kMaxRadix];
     const int radix = 1 << a.bits;
     const uint32_t mask = (uint32_t)radix - 1u;
@@ -294,13 +295,16 @@ __global__ __launch_bounds__(kSortBlock, sort_waves_per_eu(BITS, kSortBlock, kSo
 hipError_t launch_sort_hist(int src, const SortHistArgs& a, hipStream_t s) {
     int64_t work = a.n > a.fill_n ? a.n : a.fill_n;
     if (a.zero_n > work) work = a.zero_n;
-    int64_t blocks = (work + 256 * 16 - 1) / (256 * 16);
+    // Large workgroups, each flushing one histogram: every workgroup adds its
+    // counts to the global histogram with atomics, so fewer and larger ones
+    // contend less (measured against 256-thread workgroups).
+    int64_t blocks = (work + kHistBlock * 16 - 1) / (kHistBlock * 16);
     if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 1024) blocks = 1024;
     if (src == SRC_WEIGHT)
-        k_sort_hist<SRC_WEIGHT><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a);
+        k_sort_hist<SRC_WEIGHT><<<dim3((unsigned)blocks), dim3(kHistBlock), 0, s>>>(a);
     else
-        k_sort_hist<SRC_KEYS><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a);
+        k_sort_hist<SRC_KEYS><<<dim3((unsigned)blocks), dim3(kHistBlock), 0, s>>>(a);
     return hipGetLastError();
 }
 
