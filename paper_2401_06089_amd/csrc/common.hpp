@@ -50,6 +50,10 @@ struct Control {
 struct Forest {
     const int64_t* voff;   // device copy, B+1 entries
     int32_t B;
+    // Index (B > 1): the tree of every 64th edge and vertex, plus a last
+    // entry B-1, so that a lookup is two loads and a search between them.
+    const int32_t* tree_at_edge64;
+    const int32_t* tree_at_vertex64;
 
     __device__ __forceinline__ int32_t tree_of_edge(int64_t e) const {
         if (B == 1) return 0;
@@ -70,6 +74,34 @@ struct Forest {
         return lo;
     }
     __device__ __forceinline__ int64_t edge_base(int32_t b) const { return voff[b] - b; }
+    // The same searches when the answer is known to lie in [lo, hi] (then
+    // usually lo == hi and no step is taken).
+    __device__ __forceinline__ int32_t tree_of_edge_in(int64_t e, int32_t lo, int32_t hi) const {
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (voff[mid] - mid <= e) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    __device__ __forceinline__ int32_t tree_of_vertex_in(int64_t x, int32_t lo, int32_t hi) const {
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (voff[mid] <= x) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    // Through the index: the trees of 64*floor(e/64) and of the next multiple
+    // of 64 bound the tree of e (both searches are monotone in their id).
+    __device__ __forceinline__ int32_t tree_of_edge_fast(int64_t e) const {
+        if (B == 1) return 0;
+        const int64_t k = e >> 6;
+        return tree_of_edge_in(e, tree_at_edge64[k], tree_at_edge64[k + 1]);
+    }
+    __device__ __forceinline__ int32_t tree_of_vertex_fast(int64_t x) const {
+        if (B == 1) return 0;
+        const int64_t k = x >> 6;
+        return tree_of_vertex_in(x, tree_at_vertex64[k], tree_at_vertex64[k + 1]);
+    }
 };
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
         parent = (p < 0 || p >= a.m) ? -1 : a.perm[p];
     }
     if (parent >= 0 && a.forest.B > 1)
-        parent = (int32_t)(parent - a.forest.edge_base(a.forest.tree_of_edge(id)));
+        parent = (int32_t)(parent - a.forest.edge_base(a.forest.tree_of_edge_fast(id)));
     a.edge_parent[id] = parent;
 }
 
@@ -106,6 +106,18 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t value) {
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = value;
 }
 
+// The forest index: the tree of every 64th edge and vertex, closed by B-1.
+__global__ void k_forest_index(Forest f, int64_t m, int64_t n, int32_t* te, int32_t* tv) {
+    const int64_t ke = (m + 63) >> 6, kv = (n + 63) >> 6;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= ke + kv + 1; k += stride) {
+        if (k < ke) te[k] = f.tree_of_edge(k << 6);
+        else if (k == ke) te[k] = f.B - 1;
+        else if (k - ke - 1 < kv) tv[k - ke - 1] = f.tree_of_vertex((k - ke - 1) << 6);
+        else tv[kv] = f.B - 1;
+    }
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t value) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = value;
@@ -136,6 +148,14 @@ hipError_t launch_finalize(const Control* c, int32_t B, uint32_t* sticky, hipStr
 
 hipError_t launch_clear_words(uint32_t* p, int64_t n, hipStream_t s) {
     k_fill_u32<<<1, 256, 0, s>>>(p, n, 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_forest_index(const Forest& f, int64_t m, int64_t n, int32_t* te, int32_t* tv, hipStream_t s) {
+    const int64_t work = ((m + 63) >> 6) + ((n + 63) >> 6) + 2;
+    int64_t blocks = (work + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_forest_index<<<(unsigned)blocks, 256, 0, s>>>(f, m, n, te, tv);
     return hipGetLastError();
 }
 

@@ -206,6 +206,8 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t s);
 // single tree.
 hipError_t launch_zero_control(Control* c, int32_t m, int32_t n, int64_t* voff1, hipStream_t s);
 hipError_t launch_finalize(const Control* c, int32_t B, uint32_t* sticky, hipStream_t s);
+// Fills the forest index (te: (m+63)/64 + 1 entries, tv: (n+63)/64 + 1).
+hipError_t launch_forest_index(const Forest& f, int64_t m, int64_t n, int32_t* te, int32_t* tv, hipStream_t s);
 hipError_t launch_clear_words(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s);
 

@@ -130,11 +130,16 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
     if (i >= L.m) return;
     EdgeRec e;
     if (L0) {
-        const int32_t b = a.forest.tree_of_edge(i);
-        const int64_t v0 = a.forest.voff[b];
-        const int64_t nb = a.forest.voff[b + 1] - v0;
         int64_t x = a.in_u[i];
         int64_t y = a.in_v[i];
+        e.r = a.rank[i];
+        // a single tree owns every vertex; a forest's tree comes from the index
+        int64_t v0 = 0, nb = L.n;
+        if (a.forest.B > 1) {
+            const int32_t b = a.forest.tree_of_edge_fast(i);
+            v0 = a.forest.voff[b];
+            nb = a.forest.voff[b + 1] - v0;
+        }
         if (x < 0 || x >= nb || y < 0 || y >= nb) {
             raise_err(a.ctrl, kErrBadVertex);
             x = (x < 0 || x >= nb) ? 0 : x;
@@ -142,7 +147,6 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
         }
         e.u = (int32_t)(v0 + x);
         e.v = (int32_t)(v0 + y);
-        e.r = a.rank[i];
         e.id = (int32_t)i;
         a.E[i] = e;
     } else {
@@ -185,7 +189,7 @@ __device__ __forceinline__ void own_item(const LevelArgs& a, const LevelView& L,
     vinfo[x].minInc = (int32_t)(mm >> 32);
     if (L0) {
         int32_t vp = e.id;
-        if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex(x)));
+        if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex_fast(x)));
         a.vertex_parent[x] = vp;
     }
 }
@@ -287,6 +291,10 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
 __device__ __forceinline__ void jump_item(const LevelArgs& a, const LevelView& L, int64_t x, int round,
                                           int steps) {
     VInfo* vinfo = a.vinfo_all + L.off;
+    // After the first round a labelled pointer means the vertex was finished
+    // in an earlier round (label and supervertex record already written); an
+    // isolated vertex returns below either way.
+    if (round > 0 && (a.ptr[x] & kLabelFlag)) return;
     if (round == 0) {
         int32_t nn = a.ctrl->lv[a.level + 1].n;
         if (nn > a.cap_next_v) nn = a.cap_next_v;

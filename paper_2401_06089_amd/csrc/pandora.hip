@@ -87,7 +87,7 @@ struct Layout {
     int chain_bits = 8;
     int sort_cfg = kDefaultSortCfg;
     int64_t lb_words_w = 0, lb_words_c = 0;   // look-back words per pass (weight / chain sort)
-    size_t ctrl, voff, K0, K1, V0, V1, perm, rank, E0, EA, EB, min64, own, alpha, scan_lb,
+    size_t ctrl, voff, tidx, K0, K1, V0, V1, perm, rank, E0, EA, EB, min64, own, alpha, scan_lb,
         tile_excl, vinfo, ptr, svflat, lb0, lb1;
     size_t total = 0;
 };
@@ -145,6 +145,8 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
     size_t c = 0;
     L.ctrl = take(c, sizeof(Control));
     L.voff = take(c, sizeof(int64_t) * (B + 1));
+    // forest index (a single tree has none: its arrays keep their placement)
+    L.tidx = take(c, B > 1 ? sizeof(int32_t) * (((M + 63) >> 6) + ((N + 63) >> 6) + 2) : 0);
     L.K0 = take(c, 4 * M);
     L.K1 = take(c, 4 * M);
     L.V0 = take(c, 4 * M);
@@ -378,7 +380,10 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
     // until the copy has run.
     int64_t* dvoff = at<int64_t>(d, L.voff);
     if (B > 1) PD_TRY(hipMemcpyAsync(dvoff, staged_voff, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
-    const Forest forest{dvoff, B};
+    int32_t* tidx_e = B > 1 ? at<int32_t>(d, L.tidx) : nullptr;
+    int32_t* tidx_v = B > 1 ? tidx_e + ((M + 63) >> 6) + 1 : nullptr;
+    const Forest forest{dvoff, B, tidx_e, tidx_v};
+    if (B > 1) PD_TRY(launch_forest_index(forest, M, N, tidx_e, tidx_v, s));
 
     uint32_t* K[2] = {at<uint32_t>(d, L.K0), at<uint32_t>(d, L.K1)};
     int32_t* V[2] = {at<int32_t>(d, L.V0), at<int32_t>(d, L.V1)};
