@@ -62,7 +62,11 @@ typedef enum {
 
 /*
  * Dendrogram of one tree.
- *   n              number of vertices, 1 <= n <= 2^31 - 1 (edges: n-1)
+ *   n              number of vertices, 1 <= n <= 2^31 - 1 (edges: n-1); the
+ *                  vertices of all contraction levels share one int32 id
+ *                  space (about 2n ids), so a tree may have at most
+ *                  1,073,741,7xx vertices (pandora_workspace_bytes returns 0
+ *                  beyond; the call returns INVALID_ARG)
  *   u, v           int32[n-1] edge endpoints in [0, n)      (device)
  *   w              float[n-1] edge weights, no NaN          (device)
  *   edge_parent    int32[n-1] output                        (device)

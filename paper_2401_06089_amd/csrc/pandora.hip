@@ -111,7 +111,8 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
     L.M = N - B;
     const int64_t M = L.M;
     // Section 4.2: at most (m-1)/2 alpha edges per level, so at most
-    // ceil(log2(m+1)) levels; a level of a forest has at most m_j + B vertices.
+    // ceil(log2(m+1)) levels.  A level of a forest has at most m_j + B
+    // vertices, and one vertex per leaf edge of the level before.
     L.Lmax = ceil_log2(M + 1) + 2;
     L.capE.assign(L.Lmax + 2, 0);
     L.capV.assign(L.Lmax + 2, 0);
@@ -119,7 +120,7 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
     L.capV[0] = N;
     for (int j = 1; j < (int)L.capE.size(); ++j) {
         L.capE[j] = L.capE[j - 1] / 2;
-        L.capV[j] = std::min<int64_t>(L.capE[j] + B, N);
+        L.capV[j] = std::min<int64_t>(std::min<int64_t>(L.capE[j] + B, L.capE[j - 1]), N);
     }
     L.flat_cap = 0;
     for (int64_t c : L.capV) L.flat_cap += c;
@@ -168,6 +169,13 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
     L.lb1 = take(c, 8 * sortlb);
     L.total = c;
     return L;
+}
+
+// Vertices of all levels share one int32 id space (about 2n ids for one
+// tree); larger inputs are rejected up front.
+bool ids_fit(int64_t N, int32_t B) {
+    if (N <= B) return true;
+    return make_layout(N, B).flat_cap <= INT32_MAX;
 }
 
 // Pinned staging for the offsets of a stream-ordered batched call: the copy
@@ -783,6 +791,7 @@ int pandora_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const floa
                        int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream) {
     if (n < 1 || n > INT32_MAX || !vertex_parent) return PANDORA_ERR_INVALID_ARG;
     if (n > 1 && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    if (!ids_fit(n, 1)) return PANDORA_ERR_INVALID_ARG;
     const int64_t voff[2] = {0, n};
     return run_and_drain(voff, 1, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
 }
@@ -793,7 +802,7 @@ int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u,
     if (B < 1 || !voff || !vertex_parent || voff[0] != 0) return PANDORA_ERR_INVALID_ARG;
     for (int32_t b = 0; b < B; ++b)
         if (voff[b + 1] <= voff[b]) return PANDORA_ERR_INVALID_ARG;
-    if (voff[B] > INT32_MAX) return PANDORA_ERR_INVALID_ARG;
+    if (voff[B] > INT32_MAX || !ids_fit(voff[B], B)) return PANDORA_ERR_INVALID_ARG;
     if (voff[B] > B && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
     return run_and_drain(voff, B, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
 }
@@ -802,6 +811,7 @@ int pandora_dendrogram_async(int64_t n, const int32_t* u, const int32_t* v, cons
                              int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream) {
     if (n < 1 || n > INT32_MAX || !vertex_parent) return PANDORA_ERR_INVALID_ARG;
     if (n > 1 && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    if (!ids_fit(n, 1)) return PANDORA_ERR_INVALID_ARG;
     const int64_t voff[2] = {0, n};
     return run_async(voff, 1, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
 }
@@ -812,7 +822,7 @@ int pandora_dendrogram_batched_async(int32_t B, const int64_t* voff, const int32
     if (B < 1 || !voff || !vertex_parent || voff[0] != 0) return PANDORA_ERR_INVALID_ARG;
     for (int32_t b = 0; b < B; ++b)
         if (voff[b + 1] <= voff[b]) return PANDORA_ERR_INVALID_ARG;
-    if (voff[B] > INT32_MAX) return PANDORA_ERR_INVALID_ARG;
+    if (voff[B] > INT32_MAX || !ids_fit(voff[B], B)) return PANDORA_ERR_INVALID_ARG;
     if (voff[B] > B && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
     return run_async(voff, B, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
 }
@@ -853,7 +863,7 @@ int pandora_set_workspace(void* hip_stream, void* dev_ptr, size_t bytes) {
 
 size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B) {
     if (B < 1 || n_total_vertices < B || n_total_vertices > INT32_MAX) return 0;
-    if (n_total_vertices == B) return 0;
+    if (n_total_vertices == B || !ids_fit(n_total_vertices, B)) return 0;
     // enough for every tuning: the radix tile and digit width change the size
     // of the look-back buffers
     size_t most = 0;
@@ -1006,6 +1016,7 @@ int pandora_graph_create(int64_t n, const int32_t* u, const int32_t* v, const fl
     *out = nullptr;
     if (n < 1 || n > INT32_MAX || !vertex_parent) return PANDORA_ERR_INVALID_ARG;
     if (n > 1 && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    if (!ids_fit(n, 1)) return PANDORA_ERR_INVALID_ARG;
     const int64_t voff[2] = {0, n};
     return graph_create(1, voff, u, v, w, edge_parent, vertex_parent, out);
 }
@@ -1018,7 +1029,7 @@ int pandora_graph_create_batched(int32_t B, const int64_t* voff, const int32_t* 
     if (B < 1 || !voff || !vertex_parent || voff[0] != 0) return PANDORA_ERR_INVALID_ARG;
     for (int32_t b = 0; b < B; ++b)
         if (voff[b + 1] <= voff[b]) return PANDORA_ERR_INVALID_ARG;
-    if (voff[B] > INT32_MAX) return PANDORA_ERR_INVALID_ARG;
+    if (voff[B] > INT32_MAX || !ids_fit(voff[B], B)) return PANDORA_ERR_INVALID_ARG;
     if (voff[B] > B && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
     return graph_create(B, voff, u, v, w, edge_parent, vertex_parent, out);
 }

@@ -89,6 +89,7 @@ def test_argument_errors_come_back_before_any_launch(lib):
     assert lib.pandora_dendrogram(0, d, d, d, d, d, None) == INVALID_ARG
     assert lib.pandora_dendrogram(-5, d, d, d, d, d, None) == INVALID_ARG
     assert lib.pandora_dendrogram(2**31, d, d, d, d, d, None) == INVALID_ARG
+    assert lib.pandora_dendrogram(1_200_000_000, d, d, d, d, d, None) == INVALID_ARG   # ids would not fit
     assert lib.pandora_dendrogram(10, None, d, d, d, d, None) == INVALID_ARG
     assert lib.pandora_dendrogram(10, d, d, d, None, d, None) == INVALID_ARG
     assert lib.pandora_dendrogram(10, d, d, d, d, None, None) == INVALID_ARG
@@ -169,6 +170,10 @@ def test_workspace_bytes_follow_the_level_bounds(lib):
     assert lib.pandora_workspace_bytes(1, 1) == 0            # no edges, nothing to sort
     assert lib.pandora_workspace_bytes(7, 7) == 0
     assert lib.pandora_workspace_bytes(2**31, 1) == 0
+    # the level tables' vertex ids must fit int32 (about 2n of them)
+    assert lib.pandora_workspace_bytes(1_073_741_000, 1) > 0
+    assert lib.pandora_workspace_bytes(1_073_742_000, 1) == 0
+    assert lib.pandora_workspace_bytes(2**31 - 1, 1) == 0
     sizes = [lib.pandora_workspace_bytes(n, 1) for n in (10, 1000, 10**5, 10**6, 10**7)]
     assert all(a < b for a, b in zip(sizes, sizes[1:]))
     per_edge = lib.pandora_workspace_bytes(10**7, 1) / (10**7 - 1)
