@@ -146,8 +146,8 @@ def main():
     ap.add_argument("--pool", type=int, default=512, help="c5: distinct trees in the device pool")
     ap.add_argument("--streams", type=int, default=4, help="c5: server worker streams")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="c5: admission budget")
-    ap.add_argument("--max-batch-edges", type=int, default=64 << 20, help="c5: edge cap of one batch")
-    ap.add_argument("--policy", default="fifo", choices=["fifo", "small_first"], help="c5: batching order")
+    ap.add_argument("--max-batch-edges", type=int, default=8_000_000, help="c5: edge cap of one batch")
+    ap.add_argument("--policy", default="small_first", choices=["fifo", "small_first"], help="c5: batching order")
     ap.add_argument("--sample-every", type=int, default=4,
                     help="bracket the dominant kernel with HIP events on every k-th timed step")
     ap.add_argument("--calibrate-copy", action="store_true",
