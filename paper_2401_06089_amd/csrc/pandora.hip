@@ -1,18 +1,25 @@
 // Host orchestration and C ABI of libpandora.so (see include/pandora.h).
 //
-// One call runs Algorithm 1 of the paper on the device:
-//   1. weight sort: histogram + 4 one-sweep radix passes over the u32 image
-//      of the weights; the last pass emits perm (rank -> edge id) and the
-//      endpoints in rank order (global vertex ids for a forest);
-//   2. contraction levels while a level is large (k_min_incident,
-//      k_alpha_hook, k_jump until converged, k_compact), reading back one
-//      32-byte counter block per level to size the next one;
-//   3. every remaining level in one LDS-resident workgroup (k_tail);
-//   4. expansion: chain keys by the level walk (fused with the chain-key
-//      histogram), radix passes of (chain key, edge id), stitch.
+// One call runs the whole method (Sections 3.1-3.3) on the device:
+//   1. weight sort: one histogram pass and 4 one-sweep radix passes over the
+//      u32 image of the weights; the last pass writes perm (rank -> edge id)
+//      and scatters rank (edge id -> rank);
+//   2. contraction levels, level 0 in the caller's edge order: k_min_incident,
+//      k_own, k_classify, k_jump (rounds until converged), k_compact.  Either
+//      the host reads one small block back per level and launches exact
+//      grids, or every level is launched with capacity-sized grids and nothing
+//      is read back (the form a HIP graph captures).  Levels below
+//      persist_max_edges may instead run in one persistent launch (k_levels);
+//   3. every level small enough for LDS in one workgroup (k_tail);
+//   4. expansion: chain keys by the level walk (with the chain-key histogram),
+//      radix passes of (chain key, edge id), stitch.
+// A forest gets its offsets copied once and a small index (the tree of every
+// 64th edge and vertex) for tree lookups.  The plain calls wait for their
+// stream and return the status; the stream-ordered calls do not wait and leave
+// their status in a per-stream word on the device.
 //
 // Scratch memory comes from one allocation per (device, stream), kept
-// between calls and grown on demand.
+// between calls and grown on demand (or the caller's buffer).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
