@@ -67,10 +67,10 @@ def make_inputs(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def committed_traffic(workload, kernel):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
-    summary for this workload, or None when there is none or the kernel
-    sources changed since the counters were taken."""
+def committed_profile(workload):
+    """The machine-readable part of the committed rocprofv3 counter summary
+    for this workload (and its file), or (None, None) when there is none or
+    the kernel sources changed since the counters were taken."""
     import glob
     import hashlib
     import re
@@ -90,11 +90,18 @@ def committed_traffic(workload, kernel):
             continue
         if data.get("workload") != workload or data.get("source_sha256") != h.hexdigest():
             continue
-        k = data.get("kernels", {}).get(kernel)
-        if k:
-            return {"bytes_per_launch": k["traffic_bytes_per_dispatch"], "summary": os.path.relpath(md, ROOT),
-                    "rocprof_avg_us": k["avg_us_rocprof"]}
-    return None
+        return data, os.path.relpath(md, ROOT)
+    return None, None
+
+
+def committed_traffic(workload, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary."""
+    data, md = committed_profile(workload)
+    k = data.get("kernels", {}).get(kernel) if data else None
+    if not k:
+        return None
+    return {"bytes_per_launch": k["traffic_bytes_per_dispatch"], "summary": md,
+            "rocprof_avg_us": k["avg_us_rocprof"]}
 
 
 def copy_bandwidth(dev) -> float:
@@ -135,7 +142,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--stages", action="store_true", help="also report every kernel kind's time")
     ap.add_argument("--graph", action="store_true",
                     help="capture each call once into a HIP graph and replay it every step")
     ap.add_argument("--compare-per-tree", action="store_true",
@@ -306,6 +312,15 @@ def main():
                      "algorithmic_GBps": sum(s["bytes"] for s in stages.values()) / (ms_per_step / 1000) / 1e9},
     }
     out["path_hbm"]["frac"] = out["path_hbm"]["algorithmic_GBps"] / HBM_PEAK_GBS
+    # The whole path's counter-measured HBM bytes per step (all library
+    # kernels, from the committed rocprofv3 summary) over this run's step time.
+    prof, prof_md = committed_profile(args.workload)
+    if prof and prof.get("path") and not graphs:
+        per_step = prof["path"]["traffic_bytes"] / prof["path"]["steps"]
+        out["path_hbm"]["traffic_bytes_per_step"] = per_step
+        out["path_hbm"]["traffic_GBps"] = per_step / (ms_per_step / 1000) / 1e9
+        out["path_hbm"]["traffic_frac"] = out["path_hbm"]["traffic_GBps"] / HBM_PEAK_GBS
+        out["path_hbm"]["traffic_source"] = prof_md
     out["roofline"]["copy_GBps"] = copy_bandwidth(dev)
     tr = committed_traffic(args.workload, dominant)
     if tr:
@@ -314,10 +329,11 @@ def main():
         out["roofline"]["traffic_frac"] = out["roofline"]["traffic_GBps"] / HBM_PEAK_GBS
         out["roofline"]["traffic_source"] = tr["summary"]
         out["roofline"]["rocprof_avg_launch_ms"] = tr["rocprof_avg_us"] / 1000
-    if args.stages:
-        out["stages"] = {k: {"ms": s["ms"], "launches": s["launches"],
-                             "GBps": (s["bytes"] / (s["ms"] / 1000) / 1e9) if s["ms"] > 0 else None}
-                         for k, s in stages.items() if s["launches"]}
+    # Every stage's time, launches and algorithmic bandwidth, from the one
+    # profiled step that chose the dominant kernel.
+    out["stages"] = {k: {"ms": s["ms"], "launches": s["launches"],
+                         "GBps": (s["bytes"] / (s["ms"] / 1000) / 1e9) if s["ms"] > 0 else None}
+                     for k, s in stages.items() if s["launches"]}
 
     if args.compare_per_tree and args.workload == "c4":
         f = items[0][1]

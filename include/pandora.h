@@ -156,7 +156,7 @@ PANDORA_API int pandora_last_stats(int64_t* out, int cap);
  *                        level bounds, empty levels return at once [0]
  *   jump_steps           pointer-jumping steps per thread per launch [16]
  *   chain_digit_bits     radix digit width of the chain sort: 8, 9, or 0 for
- *                        8 [0]
+ *                        automatic (9 where that saves a pass, else 8) [0]
  *   sort_tile_cfg        radix tile: 0..3 = 1024, 2048, 4096, 8192 keys per
  *                        workgroup [3]
  *   persist_max_edges    levels with at most this many edges run in one

@@ -140,8 +140,9 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
         L.chain_bits = chain_bits_pref;
         L.chain_passes = std::max(1, (bits + chain_bits_pref - 1) / chain_bits_pref);
     } else {
-        L.chain_bits = 8;
-        L.chain_passes = std::max(1, (bits + 7) / 8);
+        const int p8 = std::max(1, (bits + 7) / 8), p9 = std::max(1, (bits + 8) / 9);
+        L.chain_bits = p9 < p8 ? 9 : 8;
+        L.chain_passes = p9 < p8 ? p9 : p8;
     }
 
     const int64_t E1 = std::max<int64_t>(L.capE[1], 1), E2 = std::max<int64_t>(L.capE[2], 1);
