@@ -130,9 +130,9 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
     if (i >= L.m) return;
     EdgeRec e;
     if (L0) {
-        int64_t x = a.in_u[i];
-        int64_t y = a.in_v[i];
-        e.r = a.rank[i];
+        int64_t x = load_stream(a.in_u + i);
+        int64_t y = load_stream(a.in_v + i);
+        e.r = load_stream(a.rank + i);
         // a single tree owns every vertex; a forest's tree comes from the index
         int64_t v0 = 0, nb = L.n;
         if (a.forest.B > 1) {
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
         e.u = (int32_t)(v0 + x);
         e.v = (int32_t)(v0 + y);
         e.id = (int32_t)i;
-        a.E[i] = e;
+        store_stream(reinterpret_cast<i32x4*>(a.E + i), i32x4{e.u, e.v, e.r, e.id});
     } else {
         e = a.E[i];
     }
@@ -167,7 +167,7 @@ template <bool L0>
 __device__ __forceinline__ void own_item(const LevelArgs& a, const LevelView& L, int64_t x) {
     VInfo* vinfo = a.vinfo_all + L.off;
     const bool live = x < L.n;
-    const uint64_t mm = live ? a.min64[x] : 0;
+    const uint64_t mm = live ? load_stream(a.min64 + x) : 0;
     const bool isolated = live && mm == kNoEdge;
     const uint64_t b = ballot(isolated);
     if (b != 0 && lane_id() == __ffsll((long long)b) - 1) atomicAdd(&a.ctrl->isolated, (uint32_t)popc64(b));
@@ -190,7 +190,7 @@ __device__ __forceinline__ void own_item(const LevelArgs& a, const LevelView& L,
     if (L0) {
         int32_t vp = e.id;
         if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex_fast(x)));
-        a.vertex_parent[x] = vp;
+        store_stream(a.vertex_parent + x, vp);
     }
 }
 
@@ -217,12 +217,13 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
         if (idx < L.m) {
             const uint16_t o = a.own[idx];
             a.own[idx] = 0;
-            const EdgeRec e = a.E[idx];
+            const i32x4 ev = load_stream(reinterpret_cast<const i32x4*>(a.E + idx));
+            const EdgeRec e{ev.x, ev.y, ev.z, ev.w};
             selfloop |= e.u == e.v;
             al = o == 0;
             lf = o == 0x0101;
             root[k] = e.u < e.v ? e.u : e.v;
-            a.alpha[idx] = al ? 1 : 0;
+            store_stream(a.alpha + idx, (uint8_t)(al ? 1 : 0));
         }
         const uint64_t ba = ballot(al);
         const uint64_t bl = ballot(lf);
@@ -298,9 +299,9 @@ __device__ __forceinline__ void jump_item(const LevelArgs& a, const LevelView& L
     if (round == 0) {
         int32_t nn = a.ctrl->lv[a.level + 1].n;
         if (nn > a.cap_next_v) nn = a.cap_next_v;
-        if (x < nn) a.min64[x] = kNoEdge;     // the next level starts clean
+        if (x < nn) store_stream(a.min64 + x, kNoEdge);     // the next level starts clean
     }
-    const int32_t r = vinfo[x].minInc;
+    const int32_t r = load_stream(&vinfo[x].minInc);
     if (r == kInf) {
         if (round == 0) vinfo[x].label = -1;
         return;
@@ -369,7 +370,7 @@ __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t idx = base + k * kScanBlock + tid;
-        const bool al = idx < L.m && a.alpha[idx] != 0;
+        const bool al = idx < L.m && load_stream(a.alpha + idx) != 0;
         const uint64_t ba = ballot(al);
         apre[k] = (uint32_t)popc64(ba & lt);
         amask |= (al ? 1u : 0u) << k;
@@ -392,7 +393,8 @@ __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView
     for (int k = 0; k < kScanItems; ++k) {
         if (!(amask & (1u << k))) continue;
         const int64_t idx = base + k * kScanBlock + tid;
-        const EdgeRec e = a.E[idx];
+        const i32x4 ev = load_stream(reinterpret_cast<const i32x4*>(a.E + idx));
+        const EdgeRec e{ev.x, ev.y, ev.z, ev.w};
         const int32_t lx = vinfo[e.u].label;
         const int32_t ly = vinfo[e.v].label;
         const int64_t pos = abase + s_ca[k][wave] + apre[k];
@@ -404,7 +406,7 @@ __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView
             o.v = (int32_t)vx;
             o.r = e.r;
             o.id = 0;
-            a.out[pos] = o;
+            store_stream(reinterpret_cast<i32x4*>(a.out + pos), i32x4{o.u, o.v, o.r, o.id});
             if (BID) {
                 // the next level's lightest incident edges (its min64 words
                 // were reset by this level's pointer jumping)

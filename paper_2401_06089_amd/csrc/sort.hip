@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kSortBlock, sort_waves_per_eu(BITS, kSortBlock, kSo
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = wbase + k * kWave + lane;
         key[k] = 0xffffffffu;
-        if (idx < a.n) key[k] = SRC == SRC_WEIGHT ? weight_key(a.w[idx]) : a.keys_in[idx];
+        if (idx < a.n) key[k] = SRC == SRC_WEIGHT ? weight_key(load_stream(a.w + idx)) : load_stream(a.keys_in + idx);
     }
 
     // Stable in-wave ranking: lanes holding the same digit find each other with
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kSortBlock, sort_waves_per_eu(BITS, kSortBlock, kSo
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = wbase + k * kWave + lane;
         val[k] = -1;
-        if (SRC == SRC_KEYS && idx < a.n) val[k] = a.vals_in[idx];
+        if (SRC == SRC_KEYS && idx < a.n) val[k] = load_stream(a.vals_in + idx);
     }
     __syncthreads();
     const int tile_n = (int)((a.n - base) < kSortTile ? (a.n - base) : kSortTile);
