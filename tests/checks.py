@@ -236,3 +236,100 @@ def children_sets(n, ep, vp):
         if p >= 0:
             out.setdefault(int(p), set()).add(("e", e))
     return {k: frozenset(s) for k, s in out.items()}
+
+
+def brute_flat_clusters(n, u, v, w, mcs):
+    """HDBSCAN* flat clusters straight from the definition, for tiny trees.
+
+    No dendrogram: edges are removed from the tree heaviest first (descending
+    (w, id)), and each removal splits one connected component, found by a
+    search over the remaining edges.  A component owned by a cluster passes it
+    on (one part of at least mcs vertices), spawns two new clusters (both parts
+    that large) or ends it (neither).  Stabilities are exact rational sums of
+    the departure terms count * lambda (each product rounded to fp64, as
+    defined) minus size * lambda_birth; the excess-of-mass comparison is exact.
+    Returns (labels numbered by smallest vertex id, stabilities as floats in
+    label order)."""
+    from fractions import Fraction
+    m = n - 1
+    w32 = np.asarray(w, np.float32)
+    lam = [1.0 / float(w32[e]) for e in range(m)]
+    order = list(reversed(order_key(w32)))
+    alive = set(range(m))
+
+    def component(start):
+        seen, stack = {start}, [start]
+        while stack:
+            x = stack.pop()
+            for e in alive:
+                a, b = int(u[e]), int(v[e])
+                y = b if a == x else a if b == x else None
+                if y is not None and y not in seen:
+                    seen.add(y)
+                    stack.append(y)
+        return frozenset(seen)
+
+    # cluster records: points, birth lambda, parent, exact stability
+    pts, birth, par, stab, kids = [frozenset(range(n))], [0.0], [None], [Fraction(0)], [[]]
+    owner = {frozenset(range(n)): 0}
+
+    def leave(c, count, lm):
+        stab[c] += Fraction(float(count) * lm)
+
+    for e in order:
+        a, b = int(u[e]), int(v[e])
+        K = component(a)
+        alive.discard(e)
+        K1, K2 = component(a), component(b)
+        c = owner.pop(K, None)
+        if c is None:
+            continue
+        lm = lam[e]
+        big1, big2 = len(K1) >= mcs, len(K2) >= mcs
+        if big1 and big2:
+            leave(c, len(K), lm)
+            for Kc in (K1, K2):
+                pts.append(Kc)
+                birth.append(lm)
+                par.append(c)
+                stab.append(Fraction(0))
+                kids.append([])
+                kids[c].append(len(pts) - 1)
+                owner[Kc] = len(pts) - 1
+        elif big1 or big2:
+            leave(c, len(K2) if big1 else len(K1), lm)
+            owner[K1 if big1 else K2] = c
+        else:
+            leave(c, len(K), lm)
+    for c in range(1, len(pts)):
+        stab[c] -= Fraction(float(len(pts[c])) * birth[c])
+
+    # excess of mass (children were appended after their parents)
+    value, sel = {}, {}
+    for c in range(len(pts) - 1, 0, -1):
+        if kids[c]:
+            cs = sum(value[k] for k in kids[c])
+            sel[c] = stab[c] >= cs
+            value[c] = stab[c] if sel[c] else cs
+        else:
+            sel[c], value[c] = True, stab[c]
+    chosen = []
+    for c in range(1, len(pts)):
+        a, ok = par[c], sel[c]
+        while ok and a not in (None, 0):
+            ok = not sel[a]
+            a = par[a]
+        if ok:
+            chosen.append(c)
+    lab = np.full(n, -1, np.int32)
+    for c in chosen:
+        for x in pts[c]:
+            lab[x] = c
+    out, names, st = np.full(n, -1, np.int32), {}, []
+    for x in range(n):
+        if lab[x] >= 0:
+            if lab[x] not in names:
+                names[lab[x]] = len(names)
+                st.append(float(stab[lab[x]]))
+            out[x] = names[lab[x]]
+    return out, np.array(st, np.float64)
