@@ -140,6 +140,42 @@ PANDORA_API int pandora_set_workspace(void* hip_stream, void* dev_ptr, size_t by
  * invalid sizes and for forests with no edges. */
 PANDORA_API size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B);
 
+/*
+ * HDBSCAN* flat clusters of one tree (paper, Section "HDBSCAN* Performance":
+ * the optional step after the dendrogram; cluster and selection rules of
+ * HDBSCAN*, Campello et al. 2015).  Builds the dendrogram (edge_parent,
+ * vertex_parent exactly as pandora_dendrogram) and then:
+ *   lambda(e) = 1 / w(e) in fp64 (w = +inf gives 0); every w must be > 0.
+ *   Walking down from the root, an edge node whose two children both hold
+ *   >= min_cluster_size vertices splits its cluster into two new clusters
+ *   born at its lambda; a smaller child's vertices leave the cluster there;
+ *   with no large child the cluster ends.  Stability of a cluster = sum over
+ *   its vertices of (lambda at which the vertex leaves) - (birth lambda).
+ *   Excess of mass: a cluster whose stability is >= the summed values of its
+ *   two children is selected (ties go to the parent); the root is never
+ *   selected; the chosen clusters are the selected ones with no selected
+ *   ancestor.
+ * Outputs (device memory, caller-owned):
+ *   labels[n]     chosen cluster of each vertex, numbered 0..k-1 in order of
+ *                 each cluster's smallest vertex id; -1 = noise
+ *   stability     NULL, or room for n / min_cluster_size doubles: the
+ *                 stability of cluster i at index i (fp64 sums whose order of
+ *                 additions is unspecified, so last bits may vary by run)
+ *   num_clusters  host pointer receiving k (may be NULL)
+ * min_cluster_size >= 2.  Synchronous: returns after the stream has
+ * finished the call.  Errors: INVALID_ARG (also for a weight <= 0 or NaN),
+ * the dendrogram's errors (NOT_A_TREE, BAD_VERTEX, NAN_WEIGHT),
+ * OUT_OF_MEMORY, HIP.  Uses the stream's workspace (see
+ * pandora_flat_clusters_workspace_bytes for a caller-owned one).
+ */
+PANDORA_API int pandora_flat_clusters(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                                      int32_t min_cluster_size, int32_t* edge_parent, int32_t* vertex_parent,
+                                      int32_t* labels, double* stability, int64_t* num_clusters,
+                                      void* hip_stream);
+/* Device scratch bytes pandora_flat_clusters needs for n vertices under any
+ * tuning; 0 for n < 2 or sizes the dendrogram rejects. */
+PANDORA_API size_t pandora_flat_clusters_workspace_bytes(int64_t n);
+
 /* Per-stage statistics of the last successful call on this thread:
  * out[0] = levels, out[1] = sum of edges over all levels, out[2] = pointer
  * jumping launches, out[3] = levels done in the LDS tail, out[4] = edges at

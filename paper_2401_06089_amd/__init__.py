@@ -99,6 +99,11 @@ def _load():
     lib.pandora_stream_status.restype = ctypes.c_int
     lib.pandora_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
     lib.pandora_set_workspace.restype = ctypes.c_int
+    lib.pandora_flat_clusters.argtypes = [ctypes.c_int64, vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp,
+                                          ctypes.POINTER(ctypes.c_int64), vp]
+    lib.pandora_flat_clusters.restype = ctypes.c_int
+    lib.pandora_flat_clusters_workspace_bytes.argtypes = [ctypes.c_int64]
+    lib.pandora_flat_clusters_workspace_bytes.restype = ctypes.c_size_t
     _lib = lib
     return lib
 
@@ -192,6 +197,41 @@ def dendrogram(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
         vp = torch.empty(n, dtype=torch.int32, device=dev)
         _check(dendrogram_into(n, u, v, w, ep, vp, stream))
     return ep, vp
+
+
+def flat_clusters(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, min_cluster_size: int,
+                  n: Optional[int] = None, stream=None):
+    """HDBSCAN* flat clusters (excess of mass) of one tree with n = len(w) + 1
+    vertices; every weight must be > 0.
+
+    Returns (labels[n] int32, stability[k] float64, edge_parent[n-1],
+    vertex_parent[n]) as device tensors: labels number the k chosen clusters
+    by their smallest vertex id, -1 is noise."""
+    m = w.numel()
+    if n is None:
+        n = m + 1
+    if n != m + 1 or u.numel() != m or v.numel() != m:
+        raise ValueError("a tree with n vertices has n-1 edges")
+    mcs = int(min_cluster_size)
+    dev = w.device
+    u = _as_dev(u, torch.int32, dev)
+    v = _as_dev(v, torch.int32, dev)
+    w = _as_dev(w, torch.float32, dev)
+    with torch.cuda.device(dev):
+        ep = torch.empty(m, dtype=torch.int32, device=dev)
+        vp = torch.empty(n, dtype=torch.int32, device=dev)
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+        stab = torch.empty(max(n // max(mcs, 1), 1), dtype=torch.float64, device=dev)
+        k = ctypes.c_int64(0)
+        _apply_tuning(m)
+        st = _load().pandora_flat_clusters(int(n), _dptr(u), _dptr(v), _dptr(w), mcs, _dptr(ep), _dptr(vp),
+                                           _dptr(labels), _dptr(stab), ctypes.byref(k), _stream_handle(stream))
+        _check(st)
+    return labels, stab[:k.value], ep, vp
+
+
+def flat_clusters_workspace_bytes(n: int) -> int:
+    return int(_load().pandora_flat_clusters_workspace_bytes(int(n)))
 
 
 def dendrogram_batched(voff, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,

@@ -1,0 +1,474 @@
+// HDBSCAN* flat clusters from the dendrogram on gfx950: the optional step
+// after the dendrogram that the paper names in its HDBSCAN* section, with the
+// cluster definition and the excess-of-mass selection of HDBSCAN* (Campello
+// et al. 2015, the paper's reference for it).
+//
+// The expansion leaves every dendrogram chain sorted and contiguous: runs of
+// equal chain keys, lightest edge first, in ascending key order.  An edge's
+// parent is the next edge of its run; the heaviest edge of a run hangs below
+// the run's head edge, which lies in a run whose key belongs to a later
+// contraction level.  So with the runs grouped by level:
+//   sizes     size(e_k) = size(e_{k-1}) + ext(e_k), a segmented prefix sum
+//             along each run, where ext(e) = vertices hanging at e plus the
+//             sizes of the runs headed by e (added by earlier levels).
+//             Levels run in ascending order.
+//   clusters  T(e) = e if e is born (it and its sibling both hold >= mcs
+//             vertices), else T(parent): the last birth along the run from its
+//             heavy end, seeded by T(head).  Levels run in descending order.
+// Both are ordered scans (an associative, non-commutative combine) over one
+// level's positions: per-tile reduction, one workgroup for the tile
+// carries, per-tile final pass.
+//
+// Stabilities are fp64 sums of count * lambda terms (lambda = 1 / w),
+// accumulated with atomics, so the order of additions (and the last bits)
+// vary; the selection compares them in fp64.  The excess-of-mass pass climbs
+// the cluster tree from its leaves: the second child to arrive at a parent
+// decides it (the two child values add exactly, in either order).  The chosen
+// clusters (selected, no selected ancestor) come from pointer jumping over the
+// cluster tree; labels are numbered by the smallest vertex of each cluster.
+#include "kernels.hpp"
+
+namespace pandora {
+
+namespace {
+
+constexpr int kFcItems = 4;
+constexpr int kFcTile = kFcBlock * kFcItems;
+constexpr int kFcWaves = kFcBlock / kWave;
+constexpr uint64_t kSegStart = 1ull << 63;
+
+struct OpSegSum {   // (run-start flag, sum): a start discards everything before it
+    __device__ static uint64_t identity() { return 0; }
+    __device__ static uint64_t combine(uint64_t a, uint64_t b) {
+        return (b & kSegStart) ? b : ((a & kSegStart) | ((a & ~kSegStart) + b));
+    }
+};
+struct OpLastSet {  // value + 1, 0 = unset: the last set value wins
+    __device__ static uint64_t identity() { return 0; }
+    __device__ static uint64_t combine(uint64_t a, uint64_t b) { return b ? b : a; }
+};
+struct OpSum {
+    __device__ static uint64_t identity() { return 0; }
+    __device__ static uint64_t combine(uint64_t a, uint64_t b) { return a + b; }
+};
+
+// Exclusive scan of one value per thread in thread order (whole workgroup);
+// *total receives the combination of all of them.
+template <class Op>
+__device__ uint64_t block_scan(uint64_t x, uint64_t* s_w, uint64_t* total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    uint64_t inc = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc = Op::combine(y, inc);
+    }
+    uint64_t lex = __shfl_up(inc, 1, kWave);
+    if (lane == 0) lex = Op::identity();
+    if (lane == kWave - 1) s_w[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t run = Op::identity();
+        for (int w = 0; w < kFcWaves; ++w) {
+            const uint64_t t = s_w[w];
+            s_w[w] = run;
+            run = Op::combine(run, t);
+        }
+        s_w[kFcWaves] = run;
+    }
+    __syncthreads();
+    const uint64_t res = Op::combine(s_w[wave], lex);
+    *total = s_w[kFcWaves];
+    __syncthreads();   // s_w is reused by the next scan
+    return res;
+}
+
+// ---- the three scans ------------------------------------------------------------
+
+// Sizes over one level's positions [lo, lo + cnt).
+struct SizeScan {
+    const uint32_t* skey;
+    const int32_t* sid;
+    int32_t* ext;
+    int32_t* size;
+    const int32_t* ep;
+    int64_t lo, cnt, m;
+    __device__ uint64_t load(int64_t k) const {
+        const int64_t i = lo + k;
+        const bool start = k == 0 || skey[i] != skey[i - 1];
+        const int32_t e = sid[i];
+        const uint32_t x = (e >= 0 && e < m) ? (uint32_t)ext[e] : 0u;
+        return (start ? kSegStart : 0ull) | (uint64_t)x;
+    }
+    __device__ void store(int64_t k, uint64_t incl, uint64_t) const {
+        const int64_t i = lo + k;
+        const int32_t e = sid[i];
+        if (e < 0 || e >= m) return;
+        const int32_t sz = (int32_t)(incl & ~kSegStart);
+        size[e] = sz;
+        if (k == cnt - 1 || skey[i + 1] != skey[i]) {   // heaviest edge of its run
+            const int32_t p = ep[e];
+            if (p >= 0 && p < m) atomicAdd(&ext[p], sz);
+        }
+    }
+};
+
+// Clusters over one level's positions, heaviest first: position hi-1-k.
+struct ClusterScan {
+    const uint32_t* skey;
+    const int32_t* sid;
+    const int32_t* size;
+    const int32_t* ep;
+    const uint32_t* bigcnt;
+    int32_t* T;
+    int32_t mcs, root;
+    int64_t hi, cnt, m;
+    __device__ uint64_t load(int64_t k) const {
+        const int64_t i = hi - 1 - k;
+        const int32_t e = sid[i];
+        if (e < 0 || e >= m) return 0;
+        const int32_t p = ep[e];
+        const bool parent_ok = p >= 0 && p < m;
+        if (parent_ok && size[e] >= mcs && bigcnt[p] == 2u) return (uint64_t)e + 1;   // born here
+        if (k == 0 || skey[i + 1] != skey[i]) {                                        // heavy end of a run
+            const int32_t t = parent_ok ? T[p] : root;
+            return (uint64_t)(uint32_t)t + 1;
+        }
+        return 0;
+    }
+    __device__ void store(int64_t k, uint64_t incl, uint64_t) const {
+        const int32_t e = sid[hi - 1 - k];
+        if (e >= 0 && e < m) T[e] = incl ? (int32_t)(incl - 1) : root;
+    }
+};
+
+// Label numbering over the vertices: the first vertex of each chosen cluster.
+struct NumberScan {
+    const int32_t* labels;     // chosen cluster (birth edge id) or -1
+    const int32_t* minv;
+    int32_t* cnum;
+    const double* stab;
+    double* stab_out;          // may be null
+    int64_t* count;
+    int64_t cnt;
+    __device__ uint64_t load(int64_t k) const {
+        const int32_t c = labels[k];
+        return (c >= 0 && minv[c] == (int32_t)k) ? 1ull : 0ull;
+    }
+    __device__ void store(int64_t k, uint64_t incl, uint64_t v) const {
+        if (v) {
+            const int32_t c = labels[k];
+            cnum[c] = (int32_t)(incl - 1);
+            if (stab_out) stab_out[incl - 1] = stab[c];
+        }
+        if (k == cnt - 1) *count = (int64_t)incl;
+    }
+};
+
+template <class Op, class P>
+__global__ __launch_bounds__(kFcBlock) void k_scan_reduce(P p, uint64_t* agg) {
+    __shared__ uint64_t s_w[kFcWaves + 1];
+    const int64_t base = (int64_t)blockIdx.x * kFcTile + (int64_t)threadIdx.x * kFcItems;
+    uint64_t acc = Op::identity();
+#pragma unroll
+    for (int j = 0; j < kFcItems; ++j)
+        if (base + j < p.cnt) acc = Op::combine(acc, p.load(base + j));
+    uint64_t total;
+    (void)block_scan<Op>(acc, s_w, &total);
+    if (threadIdx.x == 0) agg[blockIdx.x] = total;
+}
+
+// In place: tile aggregates -> the combination of all tiles before each.
+template <class Op>
+__global__ __launch_bounds__(kFcBlock) void k_scan_carries(uint64_t* agg, int64_t ntiles) {
+    __shared__ uint64_t s_w[kFcWaves + 1];
+    uint64_t run = Op::identity();
+    for (int64_t c0 = 0; c0 < ntiles; c0 += kFcBlock) {
+        const int64_t t = c0 + threadIdx.x;
+        const uint64_t x = t < ntiles ? agg[t] : Op::identity();
+        uint64_t total;
+        const uint64_t ex = block_scan<Op>(x, s_w, &total);
+        if (t < ntiles) agg[t] = Op::combine(run, ex);
+        run = Op::combine(run, total);
+    }
+}
+
+template <class Op, class P>
+__global__ __launch_bounds__(kFcBlock) void k_scan_final(P p, const uint64_t* carry) {
+    __shared__ uint64_t s_w[kFcWaves + 1];
+    const int64_t base = (int64_t)blockIdx.x * kFcTile + (int64_t)threadIdx.x * kFcItems;
+    uint64_t v[kFcItems];
+    uint64_t acc = Op::identity();
+#pragma unroll
+    for (int j = 0; j < kFcItems; ++j) {
+        v[j] = base + j < p.cnt ? p.load(base + j) : Op::identity();
+        acc = Op::combine(acc, v[j]);
+    }
+    uint64_t total;
+    uint64_t run = Op::combine(carry[blockIdx.x], block_scan<Op>(acc, s_w, &total));
+#pragma unroll
+    for (int j = 0; j < kFcItems; ++j) {
+        if (base + j >= p.cnt) break;
+        run = Op::combine(run, v[j]);
+        p.store(base + j, run, v[j]);
+    }
+}
+
+template <class Op, class P>
+hipError_t run_scan(const P& p, uint64_t* agg, hipStream_t s) {
+    if (p.cnt < 1) return hipSuccess;
+    const int64_t tiles = (p.cnt + kFcTile - 1) / kFcTile;
+    k_scan_reduce<Op, P><<<(unsigned)tiles, kFcBlock, 0, s>>>(p, agg);
+    k_scan_carries<Op><<<1, kFcBlock, 0, s>>>(agg, tiles);
+    k_scan_final<Op, P><<<(unsigned)tiles, kFcBlock, 0, s>>>(p, agg);
+    return hipGetLastError();
+}
+
+// ---- per-element passes ----------------------------------------------------------
+
+inline unsigned grid_for(int64_t n, int per = 256, int64_t cap = 1 << 16) {
+    int64_t b = (n + per - 1) / per;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+__global__ void k_fc_clear(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= a.m; i += stride) {
+        if (i < a.m) {
+            a.ext[i] = 0;
+            a.bigcnt[i] = 0;
+            a.bigmax[i] = 0;
+        }
+        a.stab[i] = 0.0;
+        a.csum[i] = 0.0;
+        a.arrive[i] = 0;
+        a.nchild[i] = 0;
+        a.minv[i] = INT32_MAX;
+        a.sel[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.counters[0] = 0;   // births
+        a.counters[1] = 0;   // errors
+        a.count[0] = 0;
+    }
+}
+
+// Vertices count at their parent edge; every weight must be > 0.
+__global__ void k_fc_prepare(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const int32_t p = a.vp[i];
+        if (p >= 0 && p < a.m) atomicAdd(&a.ext[p], 1);
+        else bad = true;
+        if (i < a.m && !(a.w[i] > 0.0f)) bad = true;    // also NaN
+    }
+    if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&a.counters[1], 1u);
+}
+
+// Children with >= mcs vertices per edge node (vertices never have that many).
+__global__ void k_fc_big(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.m; e += stride) {
+        const int32_t p = a.ep[e];
+        const int32_t sz = a.size[e];
+        if (p >= 0 && p < a.m && sz >= a.mcs) {
+            atomicAdd(&a.bigcnt[p], 1u);
+            atomicMax(&a.bigmax[p], sz);
+        }
+    }
+}
+
+// Departure terms count * lambda per edge node of a cluster region, the birth
+// term -size * lambda_birth, and the cluster tree (parent cluster, children).
+__global__ void k_fc_stab(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int32_t root = (int32_t)a.m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.m; e += stride) {
+        const int32_t sz = a.size[e];
+        if (sz < a.mcs) continue;
+        const int32_t c = a.T[e];
+        if (c < 0 || c > root) {
+            atomicOr(&a.counters[1], 2u);
+            continue;
+        }
+        const int32_t d = a.bigcnt[e] == 1u ? sz - a.bigmax[e] : sz;
+        const double lam = 1.0 / (double)a.w[e];
+        if (c != root) unsafeAtomicAdd(&a.stab[c], (double)d * lam);
+        if (c == (int32_t)e) {
+            const int32_t p = a.ep[e];                        // a born edge always has a parent
+            if (p < 0 || p >= a.m) {
+                atomicOr(&a.counters[1], 2u);
+                continue;
+            }
+            const double lamb = 1.0 / (double)a.w[p];
+            unsafeAtomicAdd(&a.stab[e], -((double)sz * lamb));
+            const int32_t pc = a.T[p];
+            a.cpar[e] = pc;
+            if (pc >= 0 && pc <= root) atomicAdd(&a.nchild[pc], 1u);
+            atomicAdd(&a.counters[0], 1u);
+        }
+    }
+}
+
+// Excess of mass from the leaf clusters up; the second child to arrive
+// decides its parent.  The root cluster is never selected.
+__global__ void k_fc_eom(FlatArgs a) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.m || a.T[e] != (int32_t)e || a.nchild[e] != 0u) return;
+    const int32_t root = (int32_t)a.m;
+    int32_t c = (int32_t)e;
+    double val = a.stab[c];
+    a.sel[c] = 1;
+    for (int64_t it = 0; it <= a.m; ++it) {
+        const int32_t P = a.cpar[c];
+        if (P == root || P < 0 || P > root) return;
+        unsafeAtomicAdd(&a.csum[P], val);
+        const uint32_t before =
+            __hip_atomic_fetch_add(&a.arrive[P], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (before == 0u) return;                         // the sibling decides
+        const double cs = __hip_atomic_load(&a.csum[P], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double st = a.stab[P];
+        const bool take = st >= cs;
+        a.sel[P] = take ? 1 : 0;
+        val = take ? st : cs;
+        c = P;
+    }
+    atomicOr(&a.counters[1], 4u);
+}
+
+// Pointer jumping over the cluster tree: tp[c] = the topmost selected cluster
+// on the path from c up to (not including) the root, or -1.
+__global__ void k_fc_top_init(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int32_t root = (int32_t)a.m;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= a.m; c += stride) {
+        if (c == root) {
+            a.jp[0][c] = root;
+            a.tp[0][c] = -1;
+        } else if (a.T[c] == (int32_t)c) {
+            a.jp[0][c] = a.cpar[c];
+            a.tp[0][c] = a.sel[c] ? (int32_t)c : -1;
+        }
+    }
+}
+
+__global__ void k_fc_top_round(FlatArgs a, int src) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int32_t root = (int32_t)a.m;
+    const int32_t* jin = a.jp[src];
+    const int32_t* tin = a.tp[src];
+    int32_t* jout = a.jp[src ^ 1];
+    int32_t* tout = a.tp[src ^ 1];
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= a.m; c += stride) {
+        if (c != root && a.T[c] != (int32_t)c) continue;
+        const int32_t j = jin[c];
+        if (j == root || j < 0 || j > root) {
+            jout[c] = root;
+            tout[c] = tin[c];
+        } else {
+            const int32_t tj = tin[j];
+            tout[c] = tj >= 0 ? tj : tin[c];
+            jout[c] = jin[j];
+        }
+    }
+}
+
+// Cluster of every vertex (its parent edge's cluster), its chosen cluster,
+// and the first vertex of each chosen cluster.
+__global__ void k_fc_label(FlatArgs a, int src) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int32_t root = (int32_t)a.m;
+    const int32_t* tp = a.tp[src];
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.n; x += stride) {
+        const int32_t p = a.vp[x];
+        int32_t lab = -1;
+        if (p >= 0 && p < a.m) {
+            const int32_t c = a.T[p];
+            if (c >= 0 && c < root) lab = tp[c];
+        }
+        a.labels[x] = lab;
+        if (lab >= 0) atomicMin(&a.minv[lab], (int32_t)x);
+    }
+}
+
+__global__ void k_fc_relabel(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.n; x += stride) {
+        const int32_t c = a.labels[x];
+        a.labels[x] = c >= 0 ? a.cnum[c] : -1;
+    }
+}
+
+// Position of the first key >= bound[j] in the sorted chain keys, per level.
+__global__ void k_fc_bounds(const uint32_t* skey, int64_t m, const int64_t* keys, int64_t* pos, int count) {
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= count) return;
+    const int64_t key = keys[j];
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)skey[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    pos[j] = lo;
+}
+
+}  // namespace
+
+hipError_t launch_fc_bounds(const uint32_t* skey, int64_t m, const int64_t* keys, int64_t* pos, int count,
+                            hipStream_t s) {
+    k_fc_bounds<<<1, 64, 0, s>>>(skey, m, keys, pos, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fc_prepare(const FlatArgs& a, hipStream_t s) {
+    const int64_t big = a.n > a.m + 1 ? a.n : a.m + 1;
+    k_fc_clear<<<grid_for(big), 256, 0, s>>>(a);
+    k_fc_prepare<<<grid_for(a.n), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fc_sizes(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s) {
+    SizeScan p{a.skey, a.sid, a.ext, a.size, a.ep, lo, hi - lo, a.m};
+    return run_scan<OpSegSum>(p, a.agg, s);
+}
+
+hipError_t launch_fc_big(const FlatArgs& a, hipStream_t s) {
+    k_fc_big<<<grid_for(a.m), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fc_clusters(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s) {
+    ClusterScan p{a.skey, a.sid, a.size, a.ep, a.bigcnt, a.T, a.mcs, (int32_t)a.m, hi, hi - lo, a.m};
+    return run_scan<OpLastSet>(p, a.agg, s);
+}
+
+hipError_t launch_fc_stab(const FlatArgs& a, hipStream_t s) {
+    k_fc_stab<<<grid_for(a.m), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fc_select(const FlatArgs& a, int rounds, int* final_src, hipStream_t s) {
+    k_fc_eom<<<(unsigned)((a.m + 255) / 256), 256, 0, s>>>(a);
+    k_fc_top_init<<<grid_for(a.m + 1), 256, 0, s>>>(a);
+    int src = 0;
+    for (int r = 0; r < rounds; ++r) {
+        k_fc_top_round<<<grid_for(a.m + 1), 256, 0, s>>>(a, src);
+        src ^= 1;
+    }
+    *final_src = src;
+    return hipGetLastError();
+}
+
+hipError_t launch_fc_label(const FlatArgs& a, int src, hipStream_t s) {
+    k_fc_label<<<grid_for(a.n), 256, 0, s>>>(a, src);
+    NumberScan p{a.labels, a.minv, a.cnum, a.stab, a.stab_out, a.count, a.n};
+    hipError_t e = run_scan<OpSum>(p, a.agg, s);
+    if (e != hipSuccess) return e;
+    k_fc_relabel<<<grid_for(a.n), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace pandora

@@ -201,6 +201,50 @@ struct StitchArgs {
 hipError_t launch_walk_hist(const WalkArgs& a, hipStream_t s);
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t s);
 
+// ---- HDBSCAN* flat clusters from the dendrogram ------------------------------------
+// Per-edge arrays are indexed by edge id; per-cluster arrays by the id of the
+// edge at which the cluster is born, with index m for the root cluster.
+constexpr int kFcBlock = 1024;   // threads of a scan workgroup (4 elements each)
+struct FlatArgs {
+    int64_t n, m;
+    int32_t mcs;               // minimum cluster size (>= 2)
+    const uint32_t* skey;      // chain keys, sorted (as left by the expansion)
+    const int32_t* sid;        // edge ids in chain order
+    const int32_t* ep;         // dendrogram: parent edge of every edge (-1 at the root)
+    const int32_t* vp;         // dendrogram: parent edge of every vertex
+    const float* w;
+    int32_t* ext;              // [m] vertices and run sizes hanging at each edge
+    int32_t* size;             // [m] vertices below each edge node
+    uint32_t* bigcnt;          // [m] children with >= mcs vertices
+    int32_t* bigmax;           // [m] the largest such child
+    int32_t* T;                // [m] cluster of each edge node (birth edge id, or m)
+    double* stab;              // [m+1] stability per cluster
+    double* csum;              // [m+1] summed values of the two children
+    uint32_t* arrive;          // [m+1] children that have reported
+    uint32_t* nchild;          // [m+1] children in the cluster tree (0 or 2)
+    uint8_t* sel;              // [m+1] selected by excess of mass
+    int32_t* cpar;             // [m] parent cluster of each born cluster
+    int32_t* jp[2];            // [m+1] pointer jumping: jump target
+    int32_t* tp[2];            // [m+1] pointer jumping: topmost selected so far
+    int32_t* minv;             // [m+1] smallest vertex of each chosen cluster
+    int32_t* cnum;             // [m] label of each chosen cluster
+    int32_t* labels;           // [n] output
+    double* stab_out;          // [k] output stabilities in label order (may be null)
+    int64_t* count;            // [1] number of chosen clusters
+    uint32_t* counters;        // [2] births, error bits
+    uint64_t* agg;             // scan tile aggregates
+};
+
+hipError_t launch_fc_bounds(const uint32_t* skey, int64_t m, const int64_t* keys, int64_t* pos, int count,
+                            hipStream_t s);
+hipError_t launch_fc_prepare(const FlatArgs& a, hipStream_t s);
+hipError_t launch_fc_sizes(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s);
+hipError_t launch_fc_big(const FlatArgs& a, hipStream_t s);
+hipError_t launch_fc_clusters(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s);
+hipError_t launch_fc_stab(const FlatArgs& a, hipStream_t s);
+hipError_t launch_fc_select(const FlatArgs& a, int rounds, int* final_src, hipStream_t s);
+hipError_t launch_fc_label(const FlatArgs& a, int src, hipStream_t s);
+
 // ---- misc -----------------------------------------------------------------------
 // Clears the control block; voff1, if given, receives the offsets {0, n} of a
 // single tree.

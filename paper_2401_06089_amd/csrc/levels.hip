@@ -772,6 +772,13 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         m = (int32_t)A;
         first = false;
         ++levels;
+        if (tid == 0 && entry + levels < kMaxLevels) {   // the level table covers the tail levels too
+            LevelInfo li;
+            li.m = m;
+            li.n = n;
+            li.off = off;
+            a.ctrl->lv[entry + levels] = li;
+        }
         if (off + n > a.flat_cap) {
             err |= kErrOverflow;
             break;

@@ -788,6 +788,153 @@ int run_async(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v
     return rc;
 }
 
+// ---- HDBSCAN* flat clusters ------------------------------------------------------
+
+struct FlatLayout {
+    size_t ext, size, bigcnt, bigmax, T, stab, csum, arrive, nchild, sel, cpar, jp0, jp1, tp0, tp1, minv,
+        cnum, agg, keys, pos, count, counters;
+    size_t total = 0;
+};
+
+FlatLayout make_flat_layout(int64_t N) {
+    const int64_t M = N - 1, C = M + 1;
+    const int64_t tiles = (std::max(N, C) + 4 * kFcBlock - 1) / (4 * kFcBlock) + 1;
+    FlatLayout F;
+    size_t c = 0;
+    F.ext = take(c, 4 * M);
+    F.size = take(c, 4 * M);
+    F.bigcnt = take(c, 4 * M);
+    F.bigmax = take(c, 4 * M);
+    F.T = take(c, 4 * M);
+    F.cpar = take(c, 4 * M);
+    F.cnum = take(c, 4 * M);
+    F.stab = take(c, 8 * C);
+    F.csum = take(c, 8 * C);
+    F.arrive = take(c, 4 * C);
+    F.nchild = take(c, 4 * C);
+    F.minv = take(c, 4 * C);
+    F.sel = take(c, C);
+    F.jp0 = take(c, 4 * C);
+    F.jp1 = take(c, 4 * C);
+    F.tp0 = take(c, 4 * C);
+    F.tp1 = take(c, 4 * C);
+    F.agg = take(c, 8 * tiles);
+    F.keys = take(c, 8 * (kMaxLevels + 2));
+    F.pos = take(c, 8 * (kMaxLevels + 2));
+    F.count = take(c, 8);
+    F.counters = take(c, 8);
+    F.total = c;
+    return F;
+}
+
+// The dendrogram of one tree, then its flat clusters from the chains the
+// expansion left sorted in the workspace.  Synchronous.
+int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int32_t mcs, int32_t* edge_parent,
+             int32_t* vertex_parent, int32_t* labels, double* stability, int64_t* num_clusters, hipStream_t s) {
+    const int64_t N = n, M = n - 1;
+    if (M == 0) {
+        PD_TRY(launch_fill_i32(vertex_parent, 1, -1, s));
+        PD_TRY(launch_fill_i32(labels, 1, -1, s));
+        PD_TRY(hipStreamSynchronize(s));
+        if (num_clusters) *num_clusters = 0;
+        g_last = Stats{};
+        return PANDORA_OK;
+    }
+    int dev = 0;
+    PD_TRY(hipGetDevice(&dev));
+    Workspace& ws = *workspace_for(dev, s);
+    std::lock_guard<std::mutex> lock(ws.mu);
+    const pandora_tuning_t tune = current_tuning();
+    const Layout L = make_layout(N, 1, tune.chain_digit_bits, tune.sort_tile_cfg);
+    const FlatLayout FL = make_flat_layout(N);
+    int rc = ensure(ws, L.total + FL.total, host_bytes_for(1));
+    if (rc != PANDORA_OK) return rc;
+    const Scratch sc{ws.dev, ws.host};
+    int64_t* hv = reinterpret_cast<int64_t*>(static_cast<char*>(ws.host) + sizeof(Control));
+    hv[0] = 0;
+    hv[1] = N;
+    Stats st;
+    rc = enqueue(sc, L, tune, M <= (int64_t)tune.sync_free_max_edges, hv, 1, u, v, w, edge_parent, vertex_parent,
+                 s, st);
+    if (rc != PANDORA_OK) return rc;
+    rc = finish(sc, L, 1, s, st);
+    if (rc != PANDORA_OK) return rc;
+    g_last = st;
+
+    // Levels 1..J hold chain keys; J is the last (edgeless) level.
+    const Control* hctrl = static_cast<const Control*>(sc.host);
+    const int J = (int)st.levels;
+    if (J < 1 || J + 1 >= kMaxLevels) return PANDORA_ERR_HIP;
+    std::vector<int64_t> keys(J, 0), pos(J + 1, M);
+    for (int j = 1; j <= J; ++j) keys[j - 1] = hctrl->lv[j].off - N;
+
+    char* fb = static_cast<char*>(ws.dev) + L.total;
+    FlatArgs a{};
+    a.n = N;
+    a.m = M;
+    a.mcs = mcs;
+    a.skey = at<uint32_t>(ws.dev, (L.chain_passes & 1) ? L.K1 : L.K0);
+    a.sid = at<int32_t>(ws.dev, (L.chain_passes & 1) ? L.V1 : L.V0);
+    a.ep = edge_parent;
+    a.vp = vertex_parent;
+    a.w = w;
+    a.ext = at<int32_t>(fb, FL.ext);
+    a.size = at<int32_t>(fb, FL.size);
+    a.bigcnt = at<uint32_t>(fb, FL.bigcnt);
+    a.bigmax = at<int32_t>(fb, FL.bigmax);
+    a.T = at<int32_t>(fb, FL.T);
+    a.stab = at<double>(fb, FL.stab);
+    a.csum = at<double>(fb, FL.csum);
+    a.arrive = at<uint32_t>(fb, FL.arrive);
+    a.nchild = at<uint32_t>(fb, FL.nchild);
+    a.sel = at<uint8_t>(fb, FL.sel);
+    a.cpar = at<int32_t>(fb, FL.cpar);
+    a.jp[0] = at<int32_t>(fb, FL.jp0);
+    a.jp[1] = at<int32_t>(fb, FL.jp1);
+    a.tp[0] = at<int32_t>(fb, FL.tp0);
+    a.tp[1] = at<int32_t>(fb, FL.tp1);
+    a.minv = at<int32_t>(fb, FL.minv);
+    a.cnum = at<int32_t>(fb, FL.cnum);
+    a.labels = labels;
+    a.stab_out = stability;
+    a.count = at<int64_t>(fb, FL.count);
+    a.counters = at<uint32_t>(fb, FL.counters);
+    a.agg = at<uint64_t>(fb, FL.agg);
+
+    int64_t* dkeys = at<int64_t>(fb, FL.keys);
+    int64_t* dpos = at<int64_t>(fb, FL.pos);
+    PD_TRY(hipMemcpyAsync(dkeys, keys.data(), sizeof(int64_t) * J, hipMemcpyHostToDevice, s));
+    PD_TRY(launch_fc_bounds(a.skey, M, dkeys, dpos, J, s));
+    PD_TRY(hipMemcpyAsync(pos.data(), dpos, sizeof(int64_t) * J, hipMemcpyDeviceToHost, s));
+    PD_TRY(hipStreamSynchronize(s));
+    for (int j = 0; j <= J; ++j)
+        if (pos[j] < 0 || pos[j] > M || (j > 0 && pos[j] < pos[j - 1])) return PANDORA_ERR_HIP;
+
+    // pos[j-1] .. pos[j] holds the runs of level j (pos[J] = M)
+    PD_TRY(launch_fc_prepare(a, s));
+    for (int j = 1; j <= J; ++j) PD_TRY(launch_fc_sizes(a, pos[j - 1], pos[j], s));
+    PD_TRY(launch_fc_big(a, s));
+    for (int j = J; j >= 1; --j) PD_TRY(launch_fc_clusters(a, pos[j - 1], pos[j], s));
+    PD_TRY(launch_fc_stab(a, s));
+    uint32_t hc[2] = {0, 0};
+    PD_TRY(hipMemcpyAsync(hc, a.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+    PD_TRY(hipStreamSynchronize(s));
+    if (hc[1] & 1u) return PANDORA_ERR_INVALID_ARG;      // a weight <= 0
+    if (hc[1]) return PANDORA_ERR_HIP;
+    int rounds = 1;
+    while ((int64_t(1) << (rounds - 1)) <= (int64_t)hc[0]) ++rounds;   // > log2(cluster tree depth)
+    int src = 0;
+    PD_TRY(launch_fc_select(a, rounds, &src, s));
+    PD_TRY(launch_fc_label(a, src, s));
+    int64_t k = 0;
+    PD_TRY(hipMemcpyAsync(hc, a.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+    PD_TRY(hipMemcpyAsync(&k, a.count, sizeof(k), hipMemcpyDeviceToHost, s));
+    PD_TRY(hipStreamSynchronize(s));
+    if (hc[1]) return PANDORA_ERR_HIP;
+    if (num_clusters) *num_clusters = k;
+    return PANDORA_OK;
+}
+
 }  // namespace
 }  // namespace pandora
 
@@ -867,6 +1014,29 @@ int pandora_set_workspace(void* hip_stream, void* dev_ptr, size_t bytes) {
     ws.bytes = dev_ptr ? bytes : 0;
     ws.owned = dev_ptr == nullptr;
     return PANDORA_OK;
+}
+
+int pandora_flat_clusters(int64_t n, const int32_t* u, const int32_t* v, const float* w, int32_t min_cluster_size,
+                          int32_t* edge_parent, int32_t* vertex_parent, int32_t* labels, double* stability,
+                          int64_t* num_clusters, void* hip_stream) {
+    if (n < 1 || n > INT32_MAX || min_cluster_size < 2 || !vertex_parent || !labels) return PANDORA_ERR_INVALID_ARG;
+    if (n > 1 && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    if (!ids_fit(n, 1)) return PANDORA_ERR_INVALID_ARG;
+    const int rc = run_flat(n, u, v, w, min_cluster_size, edge_parent, vertex_parent, labels, stability,
+                            num_clusters, static_cast<hipStream_t>(hip_stream));
+    if (!t_pending.empty()) {
+        (void)hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+        drain_profile();
+    }
+    return rc;
+}
+
+size_t pandora_flat_clusters_workspace_bytes(int64_t n) {
+    if (n < 2 || n > INT32_MAX || !ids_fit(n, 1)) return 0;
+    size_t most = 0;
+    for (int cfg = 0; cfg < kNumSortCfg; ++cfg)
+        for (int bits : {8, 9}) most = std::max(most, make_layout(n, 1, bits, cfg).total);
+    return most + make_flat_layout(n).total;
 }
 
 size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B) {

@@ -43,6 +43,10 @@ def lib():
     L.pandora_dendrogram_async.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 6
     L.pandora_dendrogram_batched_async.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 7
     L.pandora_set_workspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+    L.pandora_flat_clusters.argtypes = ([ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int32]
+                                        + [ctypes.c_void_p] * 6)
+    L.pandora_flat_clusters_workspace_bytes.restype = ctypes.c_size_t
+    L.pandora_flat_clusters_workspace_bytes.argtypes = [ctypes.c_int64]
     yield L
     L.pandora_set_thread_tuning(None)
 
@@ -58,9 +62,9 @@ def test_header_declares_the_api():
                  "pandora_graph_create", "pandora_graph_launch", "pandora_set_tuning"):
         assert must in names
     for must in ("pandora_dendrogram_async", "pandora_dendrogram_batched_async", "pandora_stream_status",
-                 "pandora_set_workspace"):
+                 "pandora_set_workspace", "pandora_flat_clusters", "pandora_flat_clusters_workspace_bytes"):
         assert must in names
-    assert len(names) == 20
+    assert len(names) == 22
 
 
 def test_library_exports_exactly_the_declared_functions(lib):
@@ -119,6 +123,16 @@ def test_argument_errors_come_back_before_any_launch(lib):
     # caller scratch must be 256-byte aligned and non-empty
     assert lib.pandora_set_workspace(None, ctypes.c_void_p(4096 + 8), 1 << 20) == INVALID_ARG
     assert lib.pandora_set_workspace(None, ctypes.c_void_p(4096), 0) == INVALID_ARG
+    # flat clusters: sizes, minimum cluster size and required pointers
+    k = ctypes.c_int64(-1)
+    kp = ctypes.cast(ctypes.byref(k), ctypes.c_void_p)
+    assert lib.pandora_flat_clusters(0, d, d, d, 5, d, d, d, None, kp, None) == INVALID_ARG
+    assert lib.pandora_flat_clusters(10, d, d, d, 1, d, d, d, None, kp, None) == INVALID_ARG
+    assert lib.pandora_flat_clusters(10, d, d, d, 5, d, d, None, None, kp, None) == INVALID_ARG
+    assert lib.pandora_flat_clusters(10, d, None, d, 5, d, d, d, None, kp, None) == INVALID_ARG
+    assert lib.pandora_flat_clusters(10, d, d, d, 5, None, d, d, None, kp, None) == INVALID_ARG
+    assert lib.pandora_flat_clusters(1_200_000_000, d, d, d, 5, d, d, d, None, kp, None) == INVALID_ARG
+    assert k.value == -1
 
 
 def test_tuning_validation_and_thread_scope(lib):
@@ -182,6 +196,11 @@ def test_workspace_bytes_follow_the_level_bounds(lib):
     f = lib.pandora_workspace_bytes(10**6, 1000)
     t = lib.pandora_workspace_bytes(10**6, 1)
     assert 0.9 * t <= f <= 1.2 * t
+    # flat clusters: the dendrogram's workspace plus about 80 bytes per edge
+    assert lib.pandora_flat_clusters_workspace_bytes(1) == 0
+    assert lib.pandora_flat_clusters_workspace_bytes(1_073_742_000) == 0
+    extra = lib.pandora_flat_clusters_workspace_bytes(10**7) - lib.pandora_workspace_bytes(10**7, 1)
+    assert 70 <= extra / (10**7 - 1) <= 100
 
 
 def test_profile_kinds(lib):
