@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FLAT_MCS = 100   # minimum cluster size of the flat-cluster workload
 
 WORKLOADS = {
     "c2": "two single trees, n=10,000,000 each: (a) random recursive tree, fp32 uniform [0,1) "
@@ -38,6 +39,8 @@ WORKLOADS = {
     "c2a": "random recursive tree, n=10,000,000, fp32 uniform weights",
     "c2b": "caterpillar, n=10,000,000 (9,000,000 spine + 1,000,000 leaves)",
     "c3": "preferential-attachment tree, n=50,000,000, lognormal(0,1.5) fp32 weights, 5% x10 bridges",
+    "c3flat": "HDBSCAN* flat clusters (min cluster size 100) of the preferential-attachment tree, "
+              "n=50,000,000, lognormal(0,1.5) fp32 weights, 5% x10 bridges: dendrogram + clusters per call",
     "c4": "4,096 trees, lognormal sizes in [100, 1,000,000] (~50M edges), half random-recursive "
           "half caterpillar, fp32 uniform weights, one batched call",
     "c5": "serving: Poisson arrivals at 2,000 req/s of random recursive trees with log-uniform "
@@ -64,6 +67,8 @@ def make_inputs(name):
         return [("tree", gen.c3_pref_attach(0))]
     if name == "c4":
         return [("forest", gen.c4_batched(0))]
+    if name == "c3flat":
+        return [("flat", gen.c3_pref_attach(0))]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -201,12 +206,22 @@ def main():
             calls.append(("tree", obj.n, u, v, w, ep, vp))
             total_edges += obj.m
             total_vertices += obj.n
+        elif kind == "flat":
+            ep = torch.empty(obj.m, dtype=torch.int32, device=dev)
+            vp = torch.empty(obj.n, dtype=torch.int32, device=dev)
+            lab = torch.empty(obj.n, dtype=torch.int32, device=dev)
+            stab = torch.empty(obj.n // FLAT_MCS, dtype=torch.float64, device=dev)
+            calls.append(("flat", obj.n, u, v, w, ep, vp, lab, stab))
+            total_edges += obj.m
+            total_vertices += obj.n
         else:
             calls.append(("forest", obj.voff, u, v, w))
             total_edges += obj.m_total
             total_vertices += obj.n_total
     torch.cuda.synchronize()
 
+    if args.graph and any(c[0] == "flat" for c in calls):
+        raise SystemExit("flat clusters read level sizes back during the call: no graph capture")
     graphs = []
     if args.graph:
         for c in calls:
@@ -215,12 +230,20 @@ def main():
             else:
                 graphs.append(pd.Graph(c[2], c[3], c[4], voff=c[1]))
 
+    flat_k = []
+
     def eager_step():
         for c in calls:
             if c[0] == "tree":
                 st = pd.dendrogram_into(*c[1:])
                 if st != pd.OK:
                     raise RuntimeError(f"status {st}: {pd.status_string(st)}")
+            elif c[0] == "flat":
+                n_, u_, v_, w_, ep_, vp_, lab_, stab_ = c[1:]
+                st, k = pd.flat_clusters_into(n_, u_, v_, w_, FLAT_MCS, ep_, vp_, lab_, stab_)
+                if st != pd.OK:
+                    raise RuntimeError(f"status {st}: {pd.status_string(st)}")
+                flat_k.append(k)
             else:
                 pd.dendrogram_batched(c[1], c[2], c[3], c[4])
 
@@ -359,6 +382,14 @@ def main():
         out["per_tree_calls"] = {"seconds": per_s, "edges_per_s": total_edges / per_s,
                                  "batched_speedup": per_s / (ms_per_step / 1000.0), "calls": len(trees)}
 
+    if any(kind == "flat" for kind, _ in items):
+        out["metric"] = "MST edges/sec -> dendrogram + HDBSCAN* flat clusters"
+        out["config"]["min_cluster_size"] = FLAT_MCS
+        out["config"]["clusters"] = flat_k[-1] if flat_k else None
+        if not args.no_cpu_baseline:
+            flat_baseline(out)
+        print(json.dumps(out), flush=True)
+        return
     if not args.no_cpu_baseline:
         import oracle
         log("timing the CPU oracle on the same inputs ...")
@@ -408,6 +439,23 @@ def main():
                                "seconds": cpu_s, "host_cpu": cpu_model(),
                                "host_threads_available": os.cpu_count()}
     print(json.dumps(out), flush=True)
+
+
+def flat_baseline(out):
+    """The oracle (dendrogram, then flat clusters) on a bounded sample: the
+    same generator at 2,000,000 vertices."""
+    import gen
+    from oracle.flat_clusters import flat_clusters as oracle_flat
+    sample = gen.c3_pref_attach(0, n=2_000_000)
+    log("timing the CPU oracle on a 2,000,000-vertex sample ...")
+    t1 = time.perf_counter()
+    lab, st = oracle_flat(sample.n, sample.u, sample.v, sample.w, FLAT_MCS)
+    cpu_s = time.perf_counter() - t1
+    out["cpu_baseline"] = {"value": (sample.n - 1) / cpu_s, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                           "sample": "preferential-attachment tree of 2,000,000 vertices from the same "
+                                     "generator (seed 0): oracle dendrogram (C) + flat clusters (Python)",
+                           "seconds": cpu_s, "clusters": int(st.size), "host_cpu": cpu_model(),
+                           "host_threads_available": os.cpu_count()}
 
 
 def run_serving(args, dev):

@@ -230,6 +230,17 @@ def flat_clusters(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, min_cluster
     return labels, stab[:k.value], ep, vp
 
 
+def flat_clusters_into(n: int, u, v, w, min_cluster_size: int, edge_parent, vertex_parent, labels,
+                       stability=None, stream=None) -> Tuple[int, int]:
+    """Raw call into preallocated device tensors; returns (status, number of clusters)."""
+    _apply_tuning(int(n) - 1)
+    k = ctypes.c_int64(0)
+    st = _load().pandora_flat_clusters(int(n), _dptr(u), _dptr(v), _dptr(w), int(min_cluster_size),
+                                       _dptr(edge_parent), _dptr(vertex_parent), _dptr(labels),
+                                       _dptr(stability), ctypes.byref(k), _stream_handle(stream))
+    return st, int(k.value)
+
+
 def flat_clusters_workspace_bytes(n: int) -> int:
     return int(_load().pandora_flat_clusters_workspace_bytes(int(n)))
 

@@ -21,11 +21,21 @@
 //
 // Stabilities are fp64 sums of count * lambda terms (lambda = 1 / w),
 // accumulated with atomics, so the order of additions (and the last bits)
-// vary; the selection compares them in fp64.  The excess-of-mass pass climbs
-// the cluster tree from its leaves: the second child to arrive at a parent
-// decides it (the two child values add exactly, in either order).  The chosen
-// clusters (selected, no selected ancestor) come from pointer jumping over the
-// cluster tree; labels are numbered by the smallest vertex of each cluster.
+// vary; the selection compares them in fp64.
+//
+// Excess of mass runs on the cluster tree (each cluster splits into exactly
+// two or ends), whose depth reaches tens of thousands on skewed trees.  It is
+// cut into heavy paths (each cluster continues into its child with more
+// vertices), so that any cluster has O(log n) light ancestors.  Every path is
+// laid out contiguously, bottom first, and evaluated by one wave in order:
+//   v = max(s_i, v_below + v_light_child_i)
+// exactly the oracle's operations, so values and decisions are the same.
+// A path runs once the values of all its light children are in, so there are
+// at most about log2 n rounds.  The chosen clusters (selected, no selected
+// ancestor) come from pointer jumping; labels are numbered by the smallest
+// vertex of each cluster.
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace pandora {
@@ -142,10 +152,40 @@ struct ClusterScan {
     }
 };
 
+// Dense numbering of the born clusters (edges with T(e) = e), in edge order.
+struct BirthScan {
+    const int32_t* T;
+    int32_t* clist;
+    int32_t* cidx;
+    int64_t* count;
+    int64_t cnt;
+    __device__ uint64_t load(int64_t k) const { return T[k] == (int32_t)k ? 1ull : 0ull; }
+    __device__ void store(int64_t k, uint64_t incl, uint64_t v) const {
+        if (v) {
+            clist[incl - 1] = (int32_t)k;
+            cidx[k] = (int32_t)(incl - 1);
+        }
+        if (k == cnt - 1) *count = (int64_t)incl;
+    }
+};
+
+// Offsets of the heavy paths in the layout (one entry per path head).
+struct PathScan {
+    const int32_t* up;
+    const int32_t* plen;
+    int32_t* poff;
+    int64_t cnt;
+    __device__ uint64_t load(int64_t i) const { return up[i] == (int32_t)i ? (uint64_t)plen[i] : 0ull; }
+    __device__ void store(int64_t i, uint64_t incl, uint64_t v) const {
+        if (up[i] == (int32_t)i) poff[i] = (int32_t)(incl - v);
+    }
+};
+
 // Label numbering over the vertices: the first vertex of each chosen cluster.
 struct NumberScan {
-    const int32_t* labels;     // chosen cluster (birth edge id) or -1
+    const int32_t* labels;     // chosen cluster (dense index) or -1
     const int32_t* minv;
+    const int32_t* clist;
     int32_t* cnum;
     const double* stab;
     double* stab_out;          // may be null
@@ -159,7 +199,7 @@ struct NumberScan {
         if (v) {
             const int32_t c = labels[k];
             cnum[c] = (int32_t)(incl - 1);
-            if (stab_out) stab_out[incl - 1] = stab[c];
+            if (stab_out) stab_out[incl - 1] = stab[clist[c]];
         }
         if (k == cnt - 1) *count = (int64_t)incl;
     }
@@ -235,24 +275,14 @@ inline unsigned grid_for(int64_t n, int per = 256, int64_t cap = 1 << 16) {
 
 __global__ void k_fc_clear(FlatArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= a.m; i += stride) {
-        if (i < a.m) {
-            a.ext[i] = 0;
-            a.bigcnt[i] = 0;
-            a.bigmax[i] = 0;
-        }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.m; i += stride) {
+        a.ext[i] = 0;
+        a.bigcnt[i] = 0;
+        a.bigmax[i] = 0;
         a.stab[i] = 0.0;
-        a.csum[i] = 0.0;
-        a.arrive[i] = 0;
-        a.nchild[i] = 0;
-        a.minv[i] = INT32_MAX;
-        a.sel[i] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.counters[0] = 0;   // births
-        a.counters[1] = 0;   // errors
-        a.count[0] = 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x < 4) a.counters[threadIdx.x] = 0;   // births, errors, paths done, heads
+    if (blockIdx.x == 0 && threadIdx.x < 2) a.count[threadIdx.x] = 0;
 }
 
 // Vertices count at their parent edge; every weight must be > 0.
@@ -282,7 +312,7 @@ __global__ void k_fc_big(FlatArgs a) {
 }
 
 // Departure terms count * lambda per edge node of a cluster region, the birth
-// term -size * lambda_birth, and the cluster tree (parent cluster, children).
+// term -size * lambda_birth, and each born cluster's parent cluster.
 __global__ void k_fc_stab(FlatArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int32_t root = (int32_t)a.m;
@@ -305,51 +335,188 @@ __global__ void k_fc_stab(FlatArgs a) {
             }
             const double lamb = 1.0 / (double)a.w[p];
             unsafeAtomicAdd(&a.stab[e], -((double)sz * lamb));
-            const int32_t pc = a.T[p];
-            a.cpar[e] = pc;
-            if (pc >= 0 && pc <= root) atomicAdd(&a.nchild[pc], 1u);
+            a.cpar[e] = a.T[p];
             atomicAdd(&a.counters[0], 1u);
         }
     }
 }
 
-// Excess of mass from the leaf clusters up; the second child to arrive
-// decides its parent.  The root cluster is never selected.
-__global__ void k_fc_eom(FlatArgs a) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.m || a.T[e] != (int32_t)e || a.nchild[e] != 0u) return;
-    const int32_t root = (int32_t)a.m;
-    int32_t c = (int32_t)e;
-    double val = a.stab[c];
-    a.sel[c] = 1;
-    for (int64_t it = 0; it <= a.m; ++it) {
-        const int32_t P = a.cpar[c];
-        if (P == root || P < 0 || P > root) return;
-        unsafeAtomicAdd(&a.csum[P], val);
-        const uint32_t before =
-            __hip_atomic_fetch_add(&a.arrive[P], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (before == 0u) return;                         // the sibling decides
-        const double cs = __hip_atomic_load(&a.csum[P], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double st = a.stab[P];
-        const bool take = st >= cs;
-        a.sel[P] = take ? 1 : 0;
-        val = take ? st : cs;
-        c = P;
+// ---- the cluster tree, on dense cluster indices 0..K-1 -------------------------------
+
+__global__ void k_fc_dense_clear(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= a.K; i += stride) {
+        if (i < a.K) {
+            a.heavy[i] = 0;
+            a.plen[i] = 0;
+            a.minv[i] = INT32_MAX;
+        }
+        a.sel[i] = 0;
     }
-    atomicOr(&a.counters[1], 4u);
 }
 
-// Pointer jumping over the cluster tree: tp[c] = the topmost selected cluster
-// on the path from c up to (not including) the root, or -1.
+// Parent cluster (dense; -1 = the root) and the child with more vertices.
+__global__ void k_fc_tree(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.K; i += stride) {
+        const int32_t c = a.clist[i];
+        const int32_t p = a.cpar[c];
+        int32_t pd = -1;
+        if (p >= 0 && p < a.m && a.T[p] == p) pd = a.cidx[p];
+        else if (p != (int32_t)a.m) atomicOr(&a.counters[1], 8u);
+        a.cparD[i] = pd;
+        if (pd >= 0) atomicMax((unsigned long long*)&a.heavy[pd],
+                               (unsigned long long)(((uint64_t)(uint32_t)a.size[c] << 32) | (uint32_t)i));
+    }
+}
+
+// Heavy-path heads by pointer jumping: up = path head, dist = depth below it.
+__global__ void k_fc_hp_init(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.K; i += stride) {
+        const int32_t pd = a.cparD[i];
+        const bool heavy = pd >= 0 && (uint32_t)a.heavy[pd] == (uint32_t)i;
+        a.up[0][i] = heavy ? pd : (int32_t)i;
+        a.dist[0][i] = heavy ? 1 : 0;
+    }
+}
+
+__global__ void k_fc_hp_jump(FlatArgs a, int src) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int32_t* uin = a.up[src];
+    const int32_t* din = a.dist[src];
+    int32_t* uout = a.up[src ^ 1];
+    int32_t* dout = a.dist[src ^ 1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.K; i += stride) {
+        const int32_t j = uin[i];
+        if (j == (int32_t)i || j < 0 || j >= a.K) {
+            uout[i] = j;
+            dout[i] = din[i];
+        } else {
+            uout[i] = uin[j];
+            dout[i] = din[i] + din[j];
+        }
+    }
+}
+
+__global__ void k_fc_hp_len(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.K; i += stride) {
+        const int32_t h = a.up[0][i];
+        if (h < 0 || h >= a.K || a.up[0][h] != h) {
+            atomicOr(&a.counters[1], 16u);
+            continue;
+        }
+        if (a.heavy[i] == 0) a.plen[h] = a.dist[0][i] + 1;   // the bottom: a leaf, one per path
+        if (h == (int32_t)i) atomicAdd(&a.counters[3], 1u);
+    }
+}
+
+// Layout: each path contiguous, bottom (a leaf cluster) first.
+__global__ void k_fc_hp_place(FlatArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.K; i += stride) {
+        const int32_t h = a.up[0][i];
+        if (h < 0 || h >= a.K) continue;                  // reported by k_fc_hp_len
+        const int64_t pos = (int64_t)a.poff[h] + a.plen[h] - 1 - a.dist[0][i];
+        if (pos < 0 || pos >= a.K) {
+            atomicOr(&a.counters[1], 16u);
+            continue;
+        }
+        a.lay[pos] = (int32_t)i;
+        a.posof[i] = (int32_t)pos;
+        a.s_lay[pos] = a.stab[a.clist[i]];
+        if (h == (int32_t)i) {
+            a.pending[h] = a.plen[h] - 1;                 // one light child per cluster above the bottom
+            a.ready[h] = a.plen[h] == 1 ? -1 : INT32_MAX;
+        }
+    }
+}
+
+// One round: every path whose light children were all valued in earlier
+// rounds is evaluated bottom up by one wave: the lanes load 64 consecutive
+// positions, and every lane runs the same sequential recurrence on them,
+// reading each position's operands from its lane (readlane); the lane that
+// owns a position keeps its decision.  The head's value goes to the parent's
+// light-child slot in the parent's path.
+__device__ __forceinline__ double readlane_f64(double x, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), k);
+    return __hiloint2double(hi, lo);
+}
+
+__global__ __launch_bounds__(256) void k_fc_hp_eval(FlatArgs a, int round) {
+    const int64_t h = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    const int lane = lane_id();
+    if (h >= a.K) return;                                 // whole waves
+    // every lane takes lane 0's reads, so the wave branches as one
+    const int32_t up = __builtin_amdgcn_readfirstlane(a.up[0][h]);
+    const int32_t pend = __builtin_amdgcn_readfirstlane(a.pending[h]);
+    const int32_t rdy = __builtin_amdgcn_readfirstlane(a.ready[h]);
+    if (up != (int32_t)h || pend != 0 || rdy >= round) return;
+    const int64_t base = __builtin_amdgcn_readfirstlane(a.poff[h]);
+    const int32_t len = __builtin_amdgcn_readfirstlane(a.plen[h]);
+    if (base < 0 || len < 1 || base + len > a.K) {
+        if (lane == 0) {
+            atomicOr(&a.counters[1], 16u);
+            a.pending[h] = -1;
+        }
+        return;
+    }
+    double v = 0.0;
+    double ns = 0.0, nb = 0.0;
+    if (lane < len) {
+        ns = a.s_lay[base + lane];
+        nb = a.b_lay[base + lane];
+    }
+    for (int32_t c0 = 0; c0 < len; c0 += kWave) {
+        const double ms = ns, mb = nb;
+        const int64_t idx = (int64_t)c0 + lane;
+        if (idx + kWave < len) {                          // the next chunk loads during this one
+            ns = a.s_lay[base + idx + kWave];
+            nb = a.b_lay[base + idx + kWave];
+        }
+        const int cnt = len - c0 < kWave ? len - c0 : kWave;
+        bool mine = false;
+        for (int k = 0; k < cnt; ++k) {
+            const double sk = readlane_f64(ms, k);
+            bool take;
+            if (c0 + k == 0) {                            // the bottom is a leaf cluster
+                v = sk;
+                take = true;
+            } else {
+                const double cs = v + readlane_f64(mb, k);
+                take = sk >= cs;
+                v = take ? sk : cs;
+            }
+            if (lane == k) mine = take;
+        }
+        if (idx < len) a.sel[a.lay[base + idx]] = mine ? 1 : 0;
+    }
+    if (lane == 0) {
+        a.pending[h] = -1;                                // done
+        const int32_t P = a.cparD[h];
+        if (P >= 0) {
+            a.b_lay[a.posof[P]] = v;
+            const int32_t H = a.up[0][P];
+            if (atomicSub(&a.pending[H], 1) == 1) a.ready[H] = round;
+        }
+        atomicAdd(&a.counters[2], 1u);
+    }
+}
+
+// Pointer jumping over the cluster tree (index K = the root): tp = the
+// topmost selected cluster on the path up to (not including) the root, or -1.
 __global__ void k_fc_top_init(FlatArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int32_t root = (int32_t)a.m;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= a.m; c += stride) {
+    const int32_t root = (int32_t)a.K;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= a.K; c += stride) {
         if (c == root) {
             a.jp[0][c] = root;
             a.tp[0][c] = -1;
-        } else if (a.T[c] == (int32_t)c) {
-            a.jp[0][c] = a.cpar[c];
+        } else {
+            const int32_t pd = a.cparD[c];
+            a.jp[0][c] = pd >= 0 ? pd : root;
             a.tp[0][c] = a.sel[c] ? (int32_t)c : -1;
         }
     }
@@ -357,13 +524,12 @@ __global__ void k_fc_top_init(FlatArgs a) {
 
 __global__ void k_fc_top_round(FlatArgs a, int src) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int32_t root = (int32_t)a.m;
+    const int32_t root = (int32_t)a.K;
     const int32_t* jin = a.jp[src];
     const int32_t* tin = a.tp[src];
     int32_t* jout = a.jp[src ^ 1];
     int32_t* tout = a.tp[src ^ 1];
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= a.m; c += stride) {
-        if (c != root && a.T[c] != (int32_t)c) continue;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= a.K; c += stride) {
         const int32_t j = jin[c];
         if (j == root || j < 0 || j > root) {
             jout[c] = root;
@@ -380,17 +546,16 @@ __global__ void k_fc_top_round(FlatArgs a, int src) {
 // and the first vertex of each chosen cluster.
 __global__ void k_fc_label(FlatArgs a, int src) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int32_t root = (int32_t)a.m;
     const int32_t* tp = a.tp[src];
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.n; x += stride) {
         const int32_t p = a.vp[x];
         int32_t lab = -1;
         if (p >= 0 && p < a.m) {
             const int32_t c = a.T[p];
-            if (c >= 0 && c < root) lab = tp[c];
+            if (c >= 0 && c < a.m && a.T[c] == c) lab = tp[a.cidx[c]];
         }
         a.labels[x] = lab;
-        if (lab >= 0) atomicMin(&a.minv[lab], (int32_t)x);
+        if (lab >= 0 && lab < a.K) atomicMin(&a.minv[lab], (int32_t)x);
     }
 }
 
@@ -424,8 +589,7 @@ hipError_t launch_fc_bounds(const uint32_t* skey, int64_t m, const int64_t* keys
 }
 
 hipError_t launch_fc_prepare(const FlatArgs& a, hipStream_t s) {
-    const int64_t big = a.n > a.m + 1 ? a.n : a.m + 1;
-    k_fc_clear<<<grid_for(big), 256, 0, s>>>(a);
+    k_fc_clear<<<grid_for(a.m), 256, 0, s>>>(a);
     k_fc_prepare<<<grid_for(a.n), 256, 0, s>>>(a);
     return hipGetLastError();
 }
@@ -447,24 +611,45 @@ hipError_t launch_fc_clusters(const FlatArgs& a, int64_t lo, int64_t hi, hipStre
 
 hipError_t launch_fc_stab(const FlatArgs& a, hipStream_t s) {
     k_fc_stab<<<grid_for(a.m), 256, 0, s>>>(a);
-    return hipGetLastError();
+    BirthScan p{a.T, a.clist, a.cidx, a.count, a.m};
+    return run_scan<OpSum>(p, a.agg, s);
 }
 
-hipError_t launch_fc_select(const FlatArgs& a, int rounds, int* final_src, hipStream_t s) {
-    k_fc_eom<<<(unsigned)((a.m + 255) / 256), 256, 0, s>>>(a);
-    k_fc_top_init<<<grid_for(a.m + 1), 256, 0, s>>>(a);
+hipError_t launch_fc_tree(FlatArgs& a, int rounds, hipStream_t s) {
+    k_fc_dense_clear<<<grid_for(a.K + 1), 256, 0, s>>>(a);
+    k_fc_tree<<<grid_for(a.K), 256, 0, s>>>(a);
+    k_fc_hp_init<<<grid_for(a.K), 256, 0, s>>>(a);
     int src = 0;
     for (int r = 0; r < rounds; ++r) {
-        k_fc_top_round<<<grid_for(a.m + 1), 256, 0, s>>>(a, src);
+        k_fc_hp_jump<<<grid_for(a.K), 256, 0, s>>>(a, src);
         src ^= 1;
     }
-    *final_src = src;
+    if (src == 1) {   // the final heads and depths are read from index 0 from here on
+        std::swap(a.up[0], a.up[1]);
+        std::swap(a.dist[0], a.dist[1]);
+    }
+    k_fc_hp_len<<<grid_for(a.K), 256, 0, s>>>(a);
+    PathScan p{a.up[0], a.plen, a.poff, a.K};
+    hipError_t e = run_scan<OpSum>(p, a.agg, s);
+    if (e != hipSuccess) return e;
+    k_fc_hp_place<<<grid_for(a.K), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_fc_label(const FlatArgs& a, int src, hipStream_t s) {
+hipError_t launch_fc_eval(const FlatArgs& a, int round, hipStream_t s) {
+    k_fc_hp_eval<<<(unsigned)((a.K + 3) / 4), 256, 0, s>>>(a, round);
+    return hipGetLastError();
+}
+
+hipError_t launch_fc_label(const FlatArgs& a, int rounds, hipStream_t s) {
+    k_fc_top_init<<<grid_for(a.K + 1), 256, 0, s>>>(a);
+    int src = 0;
+    for (int r = 0; r < rounds; ++r) {
+        k_fc_top_round<<<grid_for(a.K + 1), 256, 0, s>>>(a, src);
+        src ^= 1;
+    }
     k_fc_label<<<grid_for(a.n), 256, 0, s>>>(a, src);
-    NumberScan p{a.labels, a.minv, a.cnum, a.stab, a.stab_out, a.count, a.n};
+    NumberScan p{a.labels, a.minv, a.clist, a.cnum, a.stab, a.stab_out, a.count + 1, a.n};
     hipError_t e = run_scan<OpSum>(p, a.agg, s);
     if (e != hipSuccess) return e;
     k_fc_relabel<<<grid_for(a.n), 256, 0, s>>>(a);

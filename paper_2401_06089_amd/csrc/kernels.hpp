@@ -202,8 +202,9 @@ hipError_t launch_walk_hist(const WalkArgs& a, hipStream_t s);
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t s);
 
 // ---- HDBSCAN* flat clusters from the dendrogram ------------------------------------
-// Per-edge arrays are indexed by edge id; per-cluster arrays by the id of the
-// edge at which the cluster is born, with index m for the root cluster.
+// Per-edge arrays are indexed by edge id (a born cluster is named by the edge
+// where it is born, the root cluster by m); the cluster tree then works on
+// dense indices 0..K-1 of the born clusters (K for the root).
 constexpr int kFcBlock = 1024;   // threads of a scan workgroup (4 elements each)
 struct FlatArgs {
     int64_t n, m;
@@ -213,25 +214,39 @@ struct FlatArgs {
     const int32_t* ep;         // dendrogram: parent edge of every edge (-1 at the root)
     const int32_t* vp;         // dendrogram: parent edge of every vertex
     const float* w;
-    int32_t* ext;              // [m] vertices and run sizes hanging at each edge
-    int32_t* size;             // [m] vertices below each edge node
-    uint32_t* bigcnt;          // [m] children with >= mcs vertices
-    int32_t* bigmax;           // [m] the largest such child
-    int32_t* T;                // [m] cluster of each edge node (birth edge id, or m)
-    double* stab;              // [m+1] stability per cluster
-    double* csum;              // [m+1] summed values of the two children
-    uint32_t* arrive;          // [m+1] children that have reported
-    uint32_t* nchild;          // [m+1] children in the cluster tree (0 or 2)
-    uint8_t* sel;              // [m+1] selected by excess of mass
-    int32_t* cpar;             // [m] parent cluster of each born cluster
-    int32_t* jp[2];            // [m+1] pointer jumping: jump target
-    int32_t* tp[2];            // [m+1] pointer jumping: topmost selected so far
-    int32_t* minv;             // [m+1] smallest vertex of each chosen cluster
-    int32_t* cnum;             // [m] label of each chosen cluster
+    // per edge, [m]
+    int32_t* ext;              // vertices and run sizes hanging at each edge
+    int32_t* size;             // vertices below each edge node
+    uint32_t* bigcnt;          // children with >= mcs vertices
+    int32_t* bigmax;           // the largest such child
+    int32_t* T;                // cluster of each edge node (birth edge id, or m)
+    int32_t* cpar;             // parent cluster (edge id or m) of each born cluster
+    double* stab;              // stability of each born cluster
+    int32_t* cidx;             // dense index of each born cluster
+    // per cluster, dense
+    int64_t K;                 // born clusters (set by the host once counted)
+    int32_t* clist;            // [K] birth edge of each cluster
+    int32_t* cparD;            // [K] parent cluster, -1 = the root
+    uint64_t* heavy;           // [K] (size << 32 | index) of the child with more vertices
+    int32_t* up[2];            // [K] heavy paths: head (pointer jumping, double-buffered)
+    int32_t* dist[2];          // [K] depth below the head
+    int32_t* plen;             // [K] path length (at heads)
+    int32_t* poff;             // [K] first layout position of each path (at heads)
+    int32_t* posof;            // [K] layout position of each cluster
+    int32_t* lay;              // [K] cluster at each layout position
+    double* s_lay;             // [K] stabilities in layout order
+    double* b_lay;             // [K] value of each cluster's light child, in layout order
+    int32_t* pending;          // [K] light children not yet valued (at heads; -1 = done)
+    int32_t* ready;            // [K] round in which the path became ready (at heads)
+    uint8_t* sel;              // [K+1] selected by excess of mass
+    int32_t* jp[2];            // [K+1] top-down pointer jumping: jump target
+    int32_t* tp[2];            // [K+1] topmost selected cluster so far
+    int32_t* minv;             // [K] smallest vertex of each chosen cluster
+    int32_t* cnum;             // [K] label of each chosen cluster
     int32_t* labels;           // [n] output
     double* stab_out;          // [k] output stabilities in label order (may be null)
-    int64_t* count;            // [1] number of chosen clusters
-    uint32_t* counters;        // [2] births, error bits
+    int64_t* count;            // [2] born clusters, chosen clusters
+    uint32_t* counters;        // [4] births, error bits, paths evaluated, path heads
     uint64_t* agg;             // scan tile aggregates
 };
 
@@ -241,9 +256,10 @@ hipError_t launch_fc_prepare(const FlatArgs& a, hipStream_t s);
 hipError_t launch_fc_sizes(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s);
 hipError_t launch_fc_big(const FlatArgs& a, hipStream_t s);
 hipError_t launch_fc_clusters(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s);
-hipError_t launch_fc_stab(const FlatArgs& a, hipStream_t s);
-hipError_t launch_fc_select(const FlatArgs& a, int rounds, int* final_src, hipStream_t s);
-hipError_t launch_fc_label(const FlatArgs& a, int src, hipStream_t s);
+hipError_t launch_fc_stab(const FlatArgs& a, hipStream_t s);        // also numbers the born clusters
+hipError_t launch_fc_tree(FlatArgs& a, int rounds, hipStream_t s);  // heavy paths; swaps a.up/a.dist
+hipError_t launch_fc_eval(const FlatArgs& a, int round, hipStream_t s);
+hipError_t launch_fc_label(const FlatArgs& a, int rounds, hipStream_t s);
 
 // ---- misc -----------------------------------------------------------------------
 // Clears the control block; voff1, if given, receives the offsets {0, n} of a

@@ -228,13 +228,15 @@ enum ProfKind {
     PK_ZERO, PK_SORT_HIST, PK_SORT_W_FIRST, PK_SORT_W_MID, PK_SORT_W_LAST, PK_MIN_INC,
     PK_OWN, PK_CLASSIFY, PK_JUMP, PK_COMPACT, PK_TAIL, PK_WALK_HIST, PK_SORT_C_PASS, PK_STITCH,
     PK_MIN_INC_N, PK_OWN_N, PK_CLASSIFY_N, PK_JUMP_N, PK_COMPACT_N, PK_LEVELS,
+    PK_FC_PREPARE, PK_FC_SIZES, PK_FC_BIG, PK_FC_CLUSTERS, PK_FC_STAB, PK_FC_SELECT, PK_FC_LABEL,
     PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "zero_control", "sort_hist", "sort_pass_weight_first", "sort_pass_weight_mid",
     "sort_pass_weight_last", "min_incident_l0", "own_l0", "classify_l0", "jump_l0", "compact_l0",
     "tail", "walk_hist", "sort_pass_chain", "stitch", "min_incident_ln", "own_ln", "classify_ln",
-    "jump_ln", "compact_ln", "levels_persistent"};
+    "jump_ln", "compact_ln", "levels_persistent", "flat_prepare", "flat_sizes", "flat_big", "flat_clusters",
+    "flat_stability", "flat_select", "flat_label"};
 
 struct Prof {
     std::mutex mu;
@@ -791,14 +793,18 @@ int run_async(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v
 // ---- HDBSCAN* flat clusters ------------------------------------------------------
 
 struct FlatLayout {
-    size_t ext, size, bigcnt, bigmax, T, stab, csum, arrive, nchild, sel, cpar, jp0, jp1, tp0, tp1, minv,
-        cnum, agg, keys, pos, count, counters;
+    size_t ext, size, bigcnt, bigmax, T, cpar, stab, cidx, clist, cparD, heavy, up0, up1, dist0, dist1, plen,
+        poff, posof, lay, s_lay, b_lay, pending, ready, sel, jp0, jp1, tp0, tp1, minv, cnum, agg, keys, pos,
+        count, counters;
     size_t total = 0;
 };
 
-FlatLayout make_flat_layout(int64_t N) {
-    const int64_t M = N - 1, C = M + 1;
-    const int64_t tiles = (std::max(N, C) + 4 * kFcBlock - 1) / (4 * kFcBlock) + 1;
+// Born clusters come in sibling pairs of >= mcs vertices each, so there are
+// at most 2n / mcs of them.
+FlatLayout make_flat_layout(int64_t N, int32_t mcs) {
+    const int64_t M = N - 1;
+    const int64_t K = std::min<int64_t>(M, 2 * (N / std::max<int32_t>(mcs, 2)) + 2), K1 = K + 1;
+    const int64_t tiles = (std::max(N, M) + 4 * kFcBlock - 1) / (4 * kFcBlock) + 1;
     FlatLayout F;
     size_t c = 0;
     F.ext = take(c, 4 * M);
@@ -807,24 +813,43 @@ FlatLayout make_flat_layout(int64_t N) {
     F.bigmax = take(c, 4 * M);
     F.T = take(c, 4 * M);
     F.cpar = take(c, 4 * M);
-    F.cnum = take(c, 4 * M);
-    F.stab = take(c, 8 * C);
-    F.csum = take(c, 8 * C);
-    F.arrive = take(c, 4 * C);
-    F.nchild = take(c, 4 * C);
-    F.minv = take(c, 4 * C);
-    F.sel = take(c, C);
-    F.jp0 = take(c, 4 * C);
-    F.jp1 = take(c, 4 * C);
-    F.tp0 = take(c, 4 * C);
-    F.tp1 = take(c, 4 * C);
+    F.stab = take(c, 8 * M);
+    F.cidx = take(c, 4 * M);
+    F.clist = take(c, 4 * K);
+    F.cparD = take(c, 4 * K);
+    F.heavy = take(c, 8 * K);
+    F.up0 = take(c, 4 * K);
+    F.up1 = take(c, 4 * K);
+    F.dist0 = take(c, 4 * K);
+    F.dist1 = take(c, 4 * K);
+    F.plen = take(c, 4 * K);
+    F.poff = take(c, 4 * K);
+    F.posof = take(c, 4 * K);
+    F.lay = take(c, 4 * K);
+    F.s_lay = take(c, 8 * K);
+    F.b_lay = take(c, 8 * K);
+    F.pending = take(c, 4 * K);
+    F.ready = take(c, 4 * K);
+    F.sel = take(c, K1);
+    F.jp0 = take(c, 4 * K1);
+    F.jp1 = take(c, 4 * K1);
+    F.tp0 = take(c, 4 * K1);
+    F.tp1 = take(c, 4 * K1);
+    F.minv = take(c, 4 * K);
+    F.cnum = take(c, 4 * K);
     F.agg = take(c, 8 * tiles);
     F.keys = take(c, 8 * (kMaxLevels + 2));
     F.pos = take(c, 8 * (kMaxLevels + 2));
-    F.count = take(c, 8);
-    F.counters = take(c, 8);
+    F.count = take(c, 16);
+    F.counters = take(c, 16);
     F.total = c;
     return F;
+}
+
+int rounds_for(int64_t k) {   // pointer-jumping rounds that cover a depth of k
+    int r = 1;
+    while ((int64_t(1) << (r - 1)) <= k) ++r;
+    return r;
 }
 
 // The dendrogram of one tree, then its flat clusters from the chains the
@@ -846,7 +871,7 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
     std::lock_guard<std::mutex> lock(ws.mu);
     const pandora_tuning_t tune = current_tuning();
     const Layout L = make_layout(N, 1, tune.chain_digit_bits, tune.sort_tile_cfg);
-    const FlatLayout FL = make_flat_layout(N);
+    const FlatLayout FL = make_flat_layout(N, mcs);
     int rc = ensure(ws, L.total + FL.total, host_bytes_for(1));
     if (rc != PANDORA_OK) return rc;
     const Scratch sc{ws.dev, ws.host};
@@ -883,12 +908,25 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
     a.bigcnt = at<uint32_t>(fb, FL.bigcnt);
     a.bigmax = at<int32_t>(fb, FL.bigmax);
     a.T = at<int32_t>(fb, FL.T);
-    a.stab = at<double>(fb, FL.stab);
-    a.csum = at<double>(fb, FL.csum);
-    a.arrive = at<uint32_t>(fb, FL.arrive);
-    a.nchild = at<uint32_t>(fb, FL.nchild);
-    a.sel = at<uint8_t>(fb, FL.sel);
     a.cpar = at<int32_t>(fb, FL.cpar);
+    a.stab = at<double>(fb, FL.stab);
+    a.cidx = at<int32_t>(fb, FL.cidx);
+    a.clist = at<int32_t>(fb, FL.clist);
+    a.cparD = at<int32_t>(fb, FL.cparD);
+    a.heavy = at<uint64_t>(fb, FL.heavy);
+    a.up[0] = at<int32_t>(fb, FL.up0);
+    a.up[1] = at<int32_t>(fb, FL.up1);
+    a.dist[0] = at<int32_t>(fb, FL.dist0);
+    a.dist[1] = at<int32_t>(fb, FL.dist1);
+    a.plen = at<int32_t>(fb, FL.plen);
+    a.poff = at<int32_t>(fb, FL.poff);
+    a.posof = at<int32_t>(fb, FL.posof);
+    a.lay = at<int32_t>(fb, FL.lay);
+    a.s_lay = at<double>(fb, FL.s_lay);
+    a.b_lay = at<double>(fb, FL.b_lay);
+    a.pending = at<int32_t>(fb, FL.pending);
+    a.ready = at<int32_t>(fb, FL.ready);
+    a.sel = at<uint8_t>(fb, FL.sel);
     a.jp[0] = at<int32_t>(fb, FL.jp0);
     a.jp[1] = at<int32_t>(fb, FL.jp1);
     a.tp[0] = at<int32_t>(fb, FL.tp0);
@@ -910,28 +948,53 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
     for (int j = 0; j <= J; ++j)
         if (pos[j] < 0 || pos[j] > M || (j > 0 && pos[j] < pos[j - 1])) return PANDORA_ERR_HIP;
 
-    // pos[j-1] .. pos[j] holds the runs of level j (pos[J] = M)
-    PD_TRY(launch_fc_prepare(a, s));
-    for (int j = 1; j <= J; ++j) PD_TRY(launch_fc_sizes(a, pos[j - 1], pos[j], s));
-    PD_TRY(launch_fc_big(a, s));
-    for (int j = J; j >= 1; --j) PD_TRY(launch_fc_clusters(a, pos[j - 1], pos[j], s));
-    PD_TRY(launch_fc_stab(a, s));
-    uint32_t hc[2] = {0, 0};
+    // Algorithmic bytes: every array element read or written once (gathers
+    // count their element size).  pos[j-1] .. pos[j] holds the runs of level j.
+    const double Md = (double)M, Nd = (double)N;
+    PD_TIMED(PK_FC_PREPARE, 16.0 * Md + 8.0 * Nd + 4.0 * Md, launch_fc_prepare(a, s));
+    for (int j = 1; j <= J; ++j)
+        PD_TIMED(PK_FC_SIZES, 16.0 * (double)(pos[j] - pos[j - 1]), launch_fc_sizes(a, pos[j - 1], pos[j], s));
+    PD_TIMED(PK_FC_BIG, 8.0 * Md, launch_fc_big(a, s));
+    for (int j = J; j >= 1; --j)
+        PD_TIMED(PK_FC_CLUSTERS, 24.0 * (double)(pos[j] - pos[j - 1]),
+                 launch_fc_clusters(a, pos[j - 1], pos[j], s));
+    PD_TIMED(PK_FC_STAB, 24.0 * Md, launch_fc_stab(a, s));
+    uint32_t hc[4] = {0, 0, 0, 0};
+    int64_t hk[2] = {0, 0};
     PD_TRY(hipMemcpyAsync(hc, a.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+    PD_TRY(hipMemcpyAsync(hk, a.count, sizeof(hk), hipMemcpyDeviceToHost, s));
     PD_TRY(hipStreamSynchronize(s));
     if (hc[1] & 1u) return PANDORA_ERR_INVALID_ARG;      // a weight <= 0
     if (hc[1]) return PANDORA_ERR_HIP;
-    int rounds = 1;
-    while ((int64_t(1) << (rounds - 1)) <= (int64_t)hc[0]) ++rounds;   // > log2(cluster tree depth)
-    int src = 0;
-    PD_TRY(launch_fc_select(a, rounds, &src, s));
-    PD_TRY(launch_fc_label(a, src, s));
-    int64_t k = 0;
+    const int64_t K = hk[0];
+    if (K != (int64_t)hc[0] || K > (int64_t)std::min<int64_t>(M, 2 * (N / mcs) + 2)) return PANDORA_ERR_HIP;
+    if (K == 0) {                                         // no true split: every vertex is noise
+        PD_TRY(launch_fill_i32(labels, N, -1, s));
+        PD_TRY(hipStreamSynchronize(s));
+        if (num_clusters) *num_clusters = 0;
+        return PANDORA_OK;
+    }
+    a.K = K;
+    const int rounds = rounds_for(K);
+    const double Kd = (double)K;
+    PD_TIMED(PK_FC_SELECT, 40.0 * Kd + 16.0 * Kd * rounds, launch_fc_tree(a, rounds, s));
     PD_TRY(hipMemcpyAsync(hc, a.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
-    PD_TRY(hipMemcpyAsync(&k, a.count, sizeof(k), hipMemcpyDeviceToHost, s));
     PD_TRY(hipStreamSynchronize(s));
     if (hc[1]) return PANDORA_ERR_HIP;
-    if (num_clusters) *num_clusters = k;
+    const uint32_t heads = hc[3];
+    for (int round = 0;; ++round) {
+        if (round > 64) return PANDORA_ERR_HIP;           // light depth is below log2 n
+        PD_TIMED(PK_FC_SELECT, 8.0 * Kd, launch_fc_eval(a, round, s));
+        PD_TRY(hipMemcpyAsync(hc, a.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+        PD_TRY(hipStreamSynchronize(s));
+        if (hc[2] >= heads) break;
+    }
+    PD_TIMED(PK_FC_LABEL, 24.0 * Nd + 16.0 * Kd * rounds, launch_fc_label(a, rounds, s));
+    PD_TRY(hipMemcpyAsync(hc, a.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+    PD_TRY(hipMemcpyAsync(hk, a.count, sizeof(hk), hipMemcpyDeviceToHost, s));
+    PD_TRY(hipStreamSynchronize(s));
+    if (hc[1]) return PANDORA_ERR_HIP;
+    if (num_clusters) *num_clusters = hk[1];
     return PANDORA_OK;
 }
 
@@ -1036,7 +1099,7 @@ size_t pandora_flat_clusters_workspace_bytes(int64_t n) {
     size_t most = 0;
     for (int cfg = 0; cfg < kNumSortCfg; ++cfg)
         for (int bits : {8, 9}) most = std::max(most, make_layout(n, 1, bits, cfg).total);
-    return most + make_flat_layout(n).total;
+    return most + make_flat_layout(n, 2).total;
 }
 
 size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B) {
