@@ -45,7 +45,11 @@ namespace {
 constexpr int kFcItems = 4;
 constexpr int kFcTile = kFcBlock * kFcItems;
 constexpr int kFcWaves = kFcBlock / kWave;
-constexpr uint64_t kSegStart = 1ull << 63;
+constexpr uint64_t kSegStart = 1ull << 61;         // inside the 62 state bits of a look-back word
+constexpr uint64_t kLbAgg = 1ull << 62;            // look-back word: aggregate of its tile only
+constexpr uint64_t kLbInc = 2ull << 62;            // look-back word: inclusive of all tiles before
+constexpr uint64_t kLbState = (1ull << 62) - 1;
+constexpr uint32_t kLbSpinLimit = 1u << 22;
 
 struct OpSegSum {   // (run-start flag, sum): a start discards everything before it
     __device__ static uint64_t identity() { return 0; }
@@ -96,12 +100,17 @@ __device__ uint64_t block_scan(uint64_t x, uint64_t* s_w, uint64_t* total) {
 // ---- the three scans ------------------------------------------------------------
 
 // Sizes over one level's positions [lo, lo + cnt).
+// Each final size is also counted at the edge node's parent when it reaches
+// mcs (the parent's large children), so no separate pass is needed.
 struct SizeScan {
     const uint32_t* skey;
     const int32_t* sid;
     int32_t* ext;
     int32_t* size;
     const int32_t* ep;
+    uint32_t* bigcnt;
+    int32_t* bigmax;
+    int32_t mcs;
     int64_t lo, cnt, m;
     __device__ uint64_t load(int64_t k) const {
         const int64_t i = lo + k;
@@ -116,9 +125,16 @@ struct SizeScan {
         if (e < 0 || e >= m) return;
         const int32_t sz = (int32_t)(incl & ~kSegStart);
         size[e] = sz;
-        if (k == cnt - 1 || skey[i + 1] != skey[i]) {   // heaviest edge of its run
-            const int32_t p = ep[e];
-            if (p >= 0 && p < m) atomicAdd(&ext[p], sz);
+        int32_t parent;
+        if (k == cnt - 1 || skey[i + 1] != skey[i]) {   // heaviest edge of its run: hangs at the head
+            parent = ep[e];
+            if (parent >= 0 && parent < m) atomicAdd(&ext[parent], sz);
+        } else {
+            parent = sid[i + 1];
+        }
+        if (sz >= mcs && parent >= 0 && parent < m) {
+            atomicAdd(&bigcnt[parent], 1u);
+            atomicMax(&bigmax[parent], sz);
         }
     }
 };
@@ -205,38 +221,82 @@ struct NumberScan {
     }
 };
 
-template <class Op, class P>
-__global__ __launch_bounds__(kFcBlock) void k_scan_reduce(P p, uint64_t* agg) {
-    __shared__ uint64_t s_w[kFcWaves + 1];
-    const int64_t base = (int64_t)blockIdx.x * kFcTile + (int64_t)threadIdx.x * kFcItems;
-    uint64_t acc = Op::identity();
+struct ScanState {
+    uint64_t* lb;              // this scan's look-back words (cleared by the scan before)
+    uint64_t* lb_next;         // the next scan's, cleared here
+    int64_t words;
+    uint32_t* ctr;             // this scan's tile counter
+    uint32_t* ctr_next;
+    uint32_t* err;
+};
+
+// Ordered combination of the lanes' values, lane L-1 (the oldest tile) first;
+// lanes >= L contribute nothing.  Lane 0 returns the result.
+template <class Op>
+__device__ uint64_t wave_combine_desc(uint64_t v, int L) {
+    const int lane = lane_id();
+    uint64_t x = lane < L ? v : Op::identity();
 #pragma unroll
-    for (int j = 0; j < kFcItems; ++j)
-        if (base + j < p.cnt) acc = Op::combine(acc, p.load(base + j));
-    uint64_t total;
-    (void)block_scan<Op>(acc, s_w, &total);
-    if (threadIdx.x == 0) agg[blockIdx.x] = total;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_down(x, d, kWave);
+        x = Op::combine(lane + d < kWave ? y : Op::identity(), x);
+    }
+    return x;
 }
 
-// In place: tile aggregates -> the combination of all tiles before each.
+// Decoupled look-back by wave 0: lane l reads the word of tile p-l; words are
+// consumed newest first up to the nearest inclusive one (or the first tile
+// that has not published: the wave waits there).  Lane 0 gets the exclusive
+// prefix of the tile.
 template <class Op>
-__global__ __launch_bounds__(kFcBlock) void k_scan_carries(uint64_t* agg, int64_t ntiles) {
-    __shared__ uint64_t s_w[kFcWaves + 1];
-    uint64_t run = Op::identity();
-    for (int64_t c0 = 0; c0 < ntiles; c0 += kFcBlock) {
-        const int64_t t = c0 + threadIdx.x;
-        const uint64_t x = t < ntiles ? agg[t] : Op::identity();
-        uint64_t total;
-        const uint64_t ex = block_scan<Op>(x, s_w, &total);
-        if (t < ntiles) agg[t] = Op::combine(run, ex);
-        run = Op::combine(run, total);
+__device__ uint64_t scan_lookback(const uint64_t* lb, int64_t tile, uint32_t* err) {
+    const int lane = lane_id();
+    int64_t p = tile - 1;
+    uint64_t excl = Op::identity();
+    uint32_t spins = 0;
+    while (true) {
+        const int64_t q = p - lane;
+        const uint64_t w = q >= 0 ? ld_relaxed(lb + q) : (kLbInc | Op::identity());
+        const uint64_t flag = w & ~kLbState;
+        const uint64_t notready = ballot(flag == 0);
+        const int nr = notready ? __ffsll((long long)notready) - 1 : kWave;
+        const uint64_t inc = ballot(flag == kLbInc) & (nr == kWave ? ~0ull : ((1ull << nr) - 1ull));
+        if (inc) {
+            const int f = __ffsll((long long)inc) - 1;
+            return Op::combine(wave_combine_desc<Op>(w & kLbState, f + 1), excl);
+        }
+        if (nr == 0) {
+            if (++spins > kLbSpinLimit) {
+                if (lane == 0) atomicOr(err, 32u);
+                return excl;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        spins = 0;
+        excl = Op::combine(wave_combine_desc<Op>(w & kLbState, nr), excl);
+        p -= nr;
     }
 }
 
+// One pass over the range: tiles are claimed in order, each loads its
+// elements once, publishes its aggregate, looks back for its prefix and
+// finishes.  It also clears the other look-back buffer and tile counter for
+// the scan after it.
 template <class Op, class P>
-__global__ __launch_bounds__(kFcBlock) void k_scan_final(P p, const uint64_t* carry) {
+__global__ __launch_bounds__(kFcBlock) void k_scan(P p, ScanState st) {
     __shared__ uint64_t s_w[kFcWaves + 1];
-    const int64_t base = (int64_t)blockIdx.x * kFcTile + (int64_t)threadIdx.x * kFcItems;
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_excl;
+    {
+        const int64_t stride = (int64_t)gridDim.x * kFcBlock;
+        for (int64_t i = (int64_t)blockIdx.x * kFcBlock + threadIdx.x; i < st.words; i += stride) st.lb_next[i] = 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) *st.ctr_next = 0;
+    }
+    if (threadIdx.x == 0) s_tile = atomicAdd(st.ctr, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * kFcTile + (int64_t)threadIdx.x * kFcItems;
     uint64_t v[kFcItems];
     uint64_t acc = Op::identity();
 #pragma unroll
@@ -245,7 +305,17 @@ __global__ __launch_bounds__(kFcBlock) void k_scan_final(P p, const uint64_t* ca
         acc = Op::combine(acc, v[j]);
     }
     uint64_t total;
-    uint64_t run = Op::combine(carry[blockIdx.x], block_scan<Op>(acc, s_w, &total));
+    const uint64_t ex = block_scan<Op>(acc, s_w, &total);
+    if (threadIdx.x < kWave) {
+        if (threadIdx.x == 0) st_relaxed(st.lb + tile, (tile == 0 ? kLbInc : kLbAgg) | total);
+        const uint64_t excl = tile > 0 ? scan_lookback<Op>(st.lb, tile, st.err) : Op::identity();
+        if (threadIdx.x == 0) {
+            if (tile > 0) st_relaxed(st.lb + tile, kLbInc | Op::combine(excl, total));
+            s_excl = excl;
+        }
+    }
+    __syncthreads();
+    uint64_t run = Op::combine(s_excl, ex);
 #pragma unroll
     for (int j = 0; j < kFcItems; ++j) {
         if (base + j >= p.cnt) break;
@@ -255,12 +325,14 @@ __global__ __launch_bounds__(kFcBlock) void k_scan_final(P p, const uint64_t* ca
 }
 
 template <class Op, class P>
-hipError_t run_scan(const P& p, uint64_t* agg, hipStream_t s) {
+hipError_t run_scan(const P& p, const FlatArgs& a, hipStream_t s) {
     if (p.cnt < 1) return hipSuccess;
     const int64_t tiles = (p.cnt + kFcTile - 1) / kFcTile;
-    k_scan_reduce<Op, P><<<(unsigned)tiles, kFcBlock, 0, s>>>(p, agg);
-    k_scan_carries<Op><<<1, kFcBlock, 0, s>>>(agg, tiles);
-    k_scan_final<Op, P><<<(unsigned)tiles, kFcBlock, 0, s>>>(p, agg);
+    // the look-back buffers alternate between consecutive scans
+    const int cur = a.scan_seq[0] & 1;
+    ScanState st{a.lb[cur], a.lb[cur ^ 1], a.lb_words, a.scan_ctr + cur, a.scan_ctr + (cur ^ 1), &a.counters[1]};
+    ++a.scan_seq[0];
+    k_scan<Op, P><<<(unsigned)tiles, kFcBlock, 0, s>>>(p, st);
     return hipGetLastError();
 }
 
@@ -281,8 +353,12 @@ __global__ void k_fc_clear(FlatArgs a) {
         a.bigmax[i] = 0;
         a.stab[i] = 0.0;
     }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.lb_words; i += stride) a.lb[0][i] = 0;
     if (blockIdx.x == 0 && threadIdx.x < 4) a.counters[threadIdx.x] = 0;   // births, errors, paths done, heads
-    if (blockIdx.x == 0 && threadIdx.x < 2) a.count[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 2) {
+        a.count[threadIdx.x] = 0;
+        a.scan_ctr[threadIdx.x] = 0;
+    }
 }
 
 // Vertices count at their parent edge; every weight must be > 0.
@@ -296,19 +372,6 @@ __global__ void k_fc_prepare(FlatArgs a) {
         if (i < a.m && !(a.w[i] > 0.0f)) bad = true;    // also NaN
     }
     if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&a.counters[1], 1u);
-}
-
-// Children with >= mcs vertices per edge node (vertices never have that many).
-__global__ void k_fc_big(FlatArgs a) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.m; e += stride) {
-        const int32_t p = a.ep[e];
-        const int32_t sz = a.size[e];
-        if (p >= 0 && p < a.m && sz >= a.mcs) {
-            atomicAdd(&a.bigcnt[p], 1u);
-            atomicMax(&a.bigmax[p], sz);
-        }
-    }
 }
 
 // Departure terms count * lambda per edge node of a cluster region, the birth
@@ -478,18 +541,29 @@ __global__ __launch_bounds__(256) void k_fc_hp_eval(FlatArgs a, int round) {
         }
         const int cnt = len - c0 < kWave ? len - c0 : kWave;
         bool mine = false;
-        for (int k = 0; k < cnt; ++k) {
-            const double sk = readlane_f64(ms, k);
-            bool take;
-            if (c0 + k == 0) {                            // the bottom is a leaf cluster
-                v = sk;
-                take = true;
-            } else {
+        int k0 = 0;
+        if (c0 == 0) {                                    // the bottom is a leaf cluster
+            v = readlane_f64(ms, 0);
+            mine = lane == 0;
+            k0 = 1;
+        }
+        if (cnt == kWave && k0 == 0) {                    // a full chunk: constant lane indices
+#pragma unroll
+            for (int k = 0; k < kWave; ++k) {
                 const double cs = v + readlane_f64(mb, k);
-                take = sk >= cs;
+                const double sk = readlane_f64(ms, k);
+                const bool take = sk >= cs;
                 v = take ? sk : cs;
+                mine = lane == k ? take : mine;
             }
-            if (lane == k) mine = take;
+        } else {
+            for (int k = k0; k < cnt; ++k) {
+                const double cs = v + readlane_f64(mb, k);
+                const double sk = readlane_f64(ms, k);
+                const bool take = sk >= cs;
+                v = take ? sk : cs;
+                mine = lane == k ? take : mine;
+            }
         }
         if (idx < len) a.sel[a.lay[base + idx]] = mine ? 1 : 0;
     }
@@ -552,7 +626,7 @@ __global__ void k_fc_label(FlatArgs a, int src) {
         int32_t lab = -1;
         if (p >= 0 && p < a.m) {
             const int32_t c = a.T[p];
-            if (c >= 0 && c < a.m && a.T[c] == c) lab = tp[a.cidx[c]];
+            if (c >= 0 && c < a.m) lab = tp[a.cidx[c]];      // c is a born cluster or the root (m)
         }
         a.labels[x] = lab;
         if (lab >= 0 && lab < a.K) atomicMin(&a.minv[lab], (int32_t)x);
@@ -595,24 +669,19 @@ hipError_t launch_fc_prepare(const FlatArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_fc_sizes(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s) {
-    SizeScan p{a.skey, a.sid, a.ext, a.size, a.ep, lo, hi - lo, a.m};
-    return run_scan<OpSegSum>(p, a.agg, s);
-}
-
-hipError_t launch_fc_big(const FlatArgs& a, hipStream_t s) {
-    k_fc_big<<<grid_for(a.m), 256, 0, s>>>(a);
-    return hipGetLastError();
+    SizeScan p{a.skey, a.sid, a.ext, a.size, a.ep, a.bigcnt, a.bigmax, a.mcs, lo, hi - lo, a.m};
+    return run_scan<OpSegSum>(p, a, s);
 }
 
 hipError_t launch_fc_clusters(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s) {
     ClusterScan p{a.skey, a.sid, a.size, a.ep, a.bigcnt, a.T, a.mcs, (int32_t)a.m, hi, hi - lo, a.m};
-    return run_scan<OpLastSet>(p, a.agg, s);
+    return run_scan<OpLastSet>(p, a, s);
 }
 
 hipError_t launch_fc_stab(const FlatArgs& a, hipStream_t s) {
     k_fc_stab<<<grid_for(a.m), 256, 0, s>>>(a);
     BirthScan p{a.T, a.clist, a.cidx, a.count, a.m};
-    return run_scan<OpSum>(p, a.agg, s);
+    return run_scan<OpSum>(p, a, s);
 }
 
 hipError_t launch_fc_tree(FlatArgs& a, int rounds, hipStream_t s) {
@@ -630,7 +699,7 @@ hipError_t launch_fc_tree(FlatArgs& a, int rounds, hipStream_t s) {
     }
     k_fc_hp_len<<<grid_for(a.K), 256, 0, s>>>(a);
     PathScan p{a.up[0], a.plen, a.poff, a.K};
-    hipError_t e = run_scan<OpSum>(p, a.agg, s);
+    hipError_t e = run_scan<OpSum>(p, a, s);
     if (e != hipSuccess) return e;
     k_fc_hp_place<<<grid_for(a.K), 256, 0, s>>>(a);
     return hipGetLastError();
@@ -650,7 +719,7 @@ hipError_t launch_fc_label(const FlatArgs& a, int rounds, hipStream_t s) {
     }
     k_fc_label<<<grid_for(a.n), 256, 0, s>>>(a, src);
     NumberScan p{a.labels, a.minv, a.clist, a.cnum, a.stab, a.stab_out, a.count + 1, a.n};
-    hipError_t e = run_scan<OpSum>(p, a.agg, s);
+    hipError_t e = run_scan<OpSum>(p, a, s);
     if (e != hipSuccess) return e;
     k_fc_relabel<<<grid_for(a.n), 256, 0, s>>>(a);
     return hipGetLastError();

@@ -247,14 +247,16 @@ struct FlatArgs {
     double* stab_out;          // [k] output stabilities in label order (may be null)
     int64_t* count;            // [2] born clusters, chosen clusters
     uint32_t* counters;        // [4] births, error bits, paths evaluated, path heads
-    uint64_t* agg;             // scan tile aggregates
+    uint64_t* lb[2];           // scan look-back words, alternating between consecutive scans
+    int64_t lb_words;          // words per look-back buffer (tiles of the longest scan)
+    uint32_t* scan_ctr;        // [2] scan tile counters, alternating likewise
+    int* scan_seq;             // host: scans launched so far
 };
 
 hipError_t launch_fc_bounds(const uint32_t* skey, int64_t m, const int64_t* keys, int64_t* pos, int count,
                             hipStream_t s);
 hipError_t launch_fc_prepare(const FlatArgs& a, hipStream_t s);
-hipError_t launch_fc_sizes(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s);
-hipError_t launch_fc_big(const FlatArgs& a, hipStream_t s);
+hipError_t launch_fc_sizes(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s);  // also large children
 hipError_t launch_fc_clusters(const FlatArgs& a, int64_t lo, int64_t hi, hipStream_t s);
 hipError_t launch_fc_stab(const FlatArgs& a, hipStream_t s);        // also numbers the born clusters
 hipError_t launch_fc_tree(FlatArgs& a, int rounds, hipStream_t s);  // heavy paths; swaps a.up/a.dist

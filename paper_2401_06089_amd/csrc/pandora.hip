@@ -228,14 +228,14 @@ enum ProfKind {
     PK_ZERO, PK_SORT_HIST, PK_SORT_W_FIRST, PK_SORT_W_MID, PK_SORT_W_LAST, PK_MIN_INC,
     PK_OWN, PK_CLASSIFY, PK_JUMP, PK_COMPACT, PK_TAIL, PK_WALK_HIST, PK_SORT_C_PASS, PK_STITCH,
     PK_MIN_INC_N, PK_OWN_N, PK_CLASSIFY_N, PK_JUMP_N, PK_COMPACT_N, PK_LEVELS,
-    PK_FC_PREPARE, PK_FC_SIZES, PK_FC_BIG, PK_FC_CLUSTERS, PK_FC_STAB, PK_FC_SELECT, PK_FC_LABEL,
+    PK_FC_PREPARE, PK_FC_SIZES, PK_FC_CLUSTERS, PK_FC_STAB, PK_FC_SELECT, PK_FC_LABEL,
     PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "zero_control", "sort_hist", "sort_pass_weight_first", "sort_pass_weight_mid",
     "sort_pass_weight_last", "min_incident_l0", "own_l0", "classify_l0", "jump_l0", "compact_l0",
     "tail", "walk_hist", "sort_pass_chain", "stitch", "min_incident_ln", "own_ln", "classify_ln",
-    "jump_ln", "compact_ln", "levels_persistent", "flat_prepare", "flat_sizes", "flat_big", "flat_clusters",
+    "jump_ln", "compact_ln", "levels_persistent", "flat_prepare", "flat_sizes", "flat_clusters",
     "flat_stability", "flat_select", "flat_label"};
 
 struct Prof {
@@ -794,8 +794,9 @@ int run_async(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v
 
 struct FlatLayout {
     size_t ext, size, bigcnt, bigmax, T, cpar, stab, cidx, clist, cparD, heavy, up0, up1, dist0, dist1, plen,
-        poff, posof, lay, s_lay, b_lay, pending, ready, sel, jp0, jp1, tp0, tp1, minv, cnum, agg, keys, pos,
-        count, counters;
+        poff, posof, lay, s_lay, b_lay, pending, ready, sel, jp0, jp1, tp0, tp1, minv, cnum, lb0, lb1, scan_ctr,
+        keys, pos, count, counters;
+    int64_t lb_words = 0;
     size_t total = 0;
 };
 
@@ -837,7 +838,10 @@ FlatLayout make_flat_layout(int64_t N, int32_t mcs) {
     F.tp1 = take(c, 4 * K1);
     F.minv = take(c, 4 * K);
     F.cnum = take(c, 4 * K);
-    F.agg = take(c, 8 * tiles);
+    F.lb_words = tiles;
+    F.lb0 = take(c, 8 * tiles);
+    F.lb1 = take(c, 8 * tiles);
+    F.scan_ctr = take(c, 8);
     F.keys = take(c, 8 * (kMaxLevels + 2));
     F.pos = take(c, 8 * (kMaxLevels + 2));
     F.count = take(c, 16);
@@ -937,7 +941,12 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
     a.stab_out = stability;
     a.count = at<int64_t>(fb, FL.count);
     a.counters = at<uint32_t>(fb, FL.counters);
-    a.agg = at<uint64_t>(fb, FL.agg);
+    a.lb[0] = at<uint64_t>(fb, FL.lb0);
+    a.lb[1] = at<uint64_t>(fb, FL.lb1);
+    a.lb_words = FL.lb_words;
+    a.scan_ctr = at<uint32_t>(fb, FL.scan_ctr);
+    int scan_seq = 0;
+    a.scan_seq = &scan_seq;
 
     int64_t* dkeys = at<int64_t>(fb, FL.keys);
     int64_t* dpos = at<int64_t>(fb, FL.pos);
@@ -953,8 +962,7 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
     const double Md = (double)M, Nd = (double)N;
     PD_TIMED(PK_FC_PREPARE, 16.0 * Md + 8.0 * Nd + 4.0 * Md, launch_fc_prepare(a, s));
     for (int j = 1; j <= J; ++j)
-        PD_TIMED(PK_FC_SIZES, 16.0 * (double)(pos[j] - pos[j - 1]), launch_fc_sizes(a, pos[j - 1], pos[j], s));
-    PD_TIMED(PK_FC_BIG, 8.0 * Md, launch_fc_big(a, s));
+        PD_TIMED(PK_FC_SIZES, 20.0 * (double)(pos[j] - pos[j - 1]), launch_fc_sizes(a, pos[j - 1], pos[j], s));
     for (int j = J; j >= 1; --j)
         PD_TIMED(PK_FC_CLUSTERS, 24.0 * (double)(pos[j] - pos[j - 1]),
                  launch_fc_clusters(a, pos[j - 1], pos[j], s));
