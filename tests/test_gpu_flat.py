@@ -144,3 +144,22 @@ def test_large_tree_sampled_properties():
     against the oracle."""
     t = gen.rrt(2_000_000, 12, weights="lognormal")
     check(t, positive(t.w), 20)
+
+
+def test_full_size_c3_properties():
+    """The benchmark's tree (preferential attachment, 50,000,000 vertices,
+    mcs = 100), as bench.py times it: every cluster holds at least mcs
+    vertices, labels are numbered by smallest vertex, every chosen cluster's
+    stability is positive, and the label count matches the returned k."""
+    t = gen.c3_pref_attach(0)
+    print(f"flat clusters n={t.n} mcs=100", flush=True)
+    lab, st, ep, vp = run(t, t.w, 100)
+    k = st.size
+    assert k > 1000
+    assert lab.min() >= -1 and lab.max() == k - 1
+    counts = np.bincount(lab[lab >= 0], minlength=k)
+    assert (counts >= 100).all()
+    idx = np.nonzero(lab >= 0)[0]
+    firsts = idx[np.unique(lab[idx], return_index=True)[1]]   # first vertex of labels 0, 1, ...
+    assert (np.diff(firsts) > 0).all()
+    assert (st > 0).all()
