@@ -16,8 +16,10 @@
 //             vertices), else T(parent): the last birth along the run from its
 //             heavy end, seeded by T(head).  Levels run in descending order.
 // Both are ordered scans (an associative, non-commutative combine) over one
-// level's positions: per-tile reduction, one workgroup for the tile
-// carries, per-tile final pass.
+// level's positions, in one pass: tiles are claimed in order and find their
+// prefix by a decoupled look-back in which a wave combines 64 earlier tiles.
+// The size scan also counts, at each parent, the children with >= mcs
+// vertices.
 //
 // Stabilities are fp64 sums of count * lambda terms (lambda = 1 / w),
 // accumulated with atomics, so the order of additions (and the last bits)

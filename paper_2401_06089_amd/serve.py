@@ -36,6 +36,7 @@ class Request:
     w: torch.Tensor
     arrival: float                     # scheduled arrival (perf_counter seconds)
     footprint: int = 0
+    ready: Optional[torch.cuda.Event] = None   # inputs written (recorded at submit)
     future: Future = field(default_factory=Future)
     admitted: float = 0.0
     started: float = 0.0
@@ -73,8 +74,17 @@ class DendrogramServer:
 
     # ---- client side ------------------------------------------------------------
     def submit(self, req: Request) -> Future:
+        """Queue one tree.  Its tensors may still be being written by work on the
+        submitting thread's current stream: the worker's stream waits for that
+        work before reading them."""
         req.footprint = request_footprint(req.n)
+        if isinstance(req.w, torch.Tensor) and req.w.is_cuda:
+            req.ready = torch.cuda.Event()
+            req.ready.record(torch.cuda.current_stream(self.device))
         with self.cv:
+            if self.closed:
+                req.future.set_exception(RuntimeError("the server is closed"))
+                return req.future
             if req.footprint > self.budget:
                 req.future.set_exception(MemoryError(
                     f"request {req.rid} needs {req.footprint} bytes, budget is {self.budget}"))
@@ -161,6 +171,9 @@ class DendrogramServer:
         voff = np.zeros(len(batch) + 1, dtype=np.int64)
         np.cumsum(sizes, out=voff[1:])
         with torch.cuda.stream(stream):
+            for r in batch:
+                if r.ready is not None:
+                    stream.wait_event(r.ready)
             if len(batch) == 1:
                 u, v, w = batch[0].u, batch[0].v, batch[0].w
             else:

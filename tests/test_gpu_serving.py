@@ -72,3 +72,30 @@ def test_server_rejects_oversized_request():
     with pytest.raises(MemoryError):
         r.future.result(timeout=10)
     srv.close()
+
+
+def test_server_waits_for_inputs_still_being_written():
+    """A client writes a request's weights on its own stream, behind a long
+    GPU spin, and submits at once: the worker's stream must wait for that
+    write (the event recorded at submit), so the result is still the
+    oracle's."""
+    from paper_2401_06089_amd.serve import DendrogramServer, Request
+
+    dev = torch.device("cuda:0")
+    t = gen.rrt(200_000, 5, weights="lognormal")
+    u = torch.from_numpy(t.u).to(dev)
+    v = torch.from_numpy(t.v).to(dev)
+    w_host = torch.from_numpy(t.w).pin_memory()
+    srv = DendrogramServer(1 << 36, streams=2)
+    client = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(client):
+        w = torch.zeros(t.n - 1, dtype=torch.float32, device=dev)   # wrong until the copy lands
+        torch.cuda._sleep(200_000_000)                               # on the order of 0.1 s of spinning
+        w.copy_(w_host, non_blocking=True)
+        r = Request(0, t.n, u, v, w, arrival=time.perf_counter())
+        srv.submit(r)
+    ep, vp = r.future.result(timeout=120)
+    srv.close()
+    oep, ovp = oracle.dendrogram(t.n, t.u, t.v, t.w)
+    assert np.array_equal(ep.cpu().numpy(), oep) and np.array_equal(vp.cpu().numpy(), ovp)

@@ -73,3 +73,12 @@ def test_oversized_request_is_rejected_at_submit():
 def test_unknown_policy():
     with pytest.raises(ValueError):
         DendrogramServer(1 << 30, streams=0, policy="lifo")
+
+
+def test_submit_after_close_fails_the_request():
+    srv = DendrogramServer(10**12, streams=0)
+    srv.close()
+    r = Request(0, 100, None, None, None, arrival=0.0)
+    srv.submit(r)
+    with pytest.raises(RuntimeError):
+        r.future.result(timeout=1)
