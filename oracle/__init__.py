@@ -9,7 +9,9 @@ loads it, and the two share no code.
 becomes the parent of the two clusters it merges.  ``checks.py`` holds the
 independent checks that pin it (brute force, closed forms, invariants).
 ``flat_clusters.py`` takes HDBSCAN* flat clusters from that dendrogram
-(pinned by ``tests/test_flat_oracle.py``).
+(pinned by ``tests/test_flat_oracle.py``), and ``emst.py`` builds the
+mutual-reachability MST of a point cloud that HDBSCAN* starts from (pinned by
+``tests/test_emst_oracle.py``).
 
 Status codes: 0 ok, 1 invalid argument, 2 not a tree, 3 NaN weight,
 6 vertex id out of range.
