@@ -172,6 +172,28 @@ PANDORA_API int pandora_flat_clusters(int64_t n, const int32_t* u, const int32_t
                                       int32_t min_cluster_size, int32_t* edge_parent, int32_t* vertex_parent,
                                       int32_t* labels, double* stability, int64_t* num_clusters,
                                       void* hip_stream);
+/*
+ * Mutual-reachability minimum spanning tree of a point cloud: the tree that
+ * HDBSCAN* builds before the dendrogram (paper, Section "HDBSCAN*
+ * Performance"; definitions of Campello et al. 2015).
+ *   points   device, n x dim fp32, row-major; 1 <= dim <= 4; finite
+ *   min_pts  1..min(32, n): the core distance of a point is the distance to
+ *            its (min_pts - 1)-th nearest other point (0 for min_pts = 1)
+ *   mutual reachability = max(core(i), core(j), |x_i - x_j|), evaluated on
+ *   squared distances in fp64 (coordinates summed in order, each operation
+ *   rounded on its own); edges are ordered by (squared mutual reachability,
+ *   min(i, j), max(i, j)), which makes the tree unique.
+ * Outputs (device, caller-owned, n-1 entries each): the tree's edges in that
+ * order, u[k] < v[k], with weights w64 = sqrt(squared mutual reachability)
+ * (correctly rounded; may be NULL) and w32 = its fp32 rounding, ready for
+ * pandora_dendrogram / pandora_flat_clusters (edge k = k-th in the order).
+ * Brute force: O(n^2) distance evaluations per Boruvka round, at most
+ * about log2 n rounds; n <= 2^24.  Synchronous.  Errors: INVALID_ARG (also
+ * for a non-finite coordinate), OUT_OF_MEMORY, HIP.
+ */
+PANDORA_API int pandora_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32_t* u, int32_t* v,
+                             double* w64, float* w32, void* hip_stream);
+
 /* Device scratch bytes pandora_flat_clusters needs for n vertices under any
  * tuning; 0 for n < 2 or sizes the dendrogram rejects. */
 PANDORA_API size_t pandora_flat_clusters_workspace_bytes(int64_t n);

@@ -102,6 +102,8 @@ def _load():
     lib.pandora_flat_clusters.argtypes = [ctypes.c_int64, vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp,
                                           ctypes.POINTER(ctypes.c_int64), vp]
     lib.pandora_flat_clusters.restype = ctypes.c_int
+    lib.pandora_emst.argtypes = [ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
+    lib.pandora_emst.restype = ctypes.c_int
     lib.pandora_flat_clusters_workspace_bytes.argtypes = [ctypes.c_int64]
     lib.pandora_flat_clusters_workspace_bytes.restype = ctypes.c_size_t
     _lib = lib
@@ -239,6 +241,36 @@ def flat_clusters_into(n: int, u, v, w, min_cluster_size: int, edge_parent, vert
                                        _dptr(edge_parent), _dptr(vertex_parent), _dptr(labels),
                                        _dptr(stability), ctypes.byref(k), _stream_handle(stream))
     return st, int(k.value)
+
+
+def emst(points: torch.Tensor, min_pts: int, stream=None):
+    """Mutual-reachability MST of an (n, dim) float32 device tensor of points
+    (dim <= 4).  Returns (u, v, w64, w32): the n-1 edges in ascending (weight,
+    u, v) order, u < v, with fp64 and fp32 weights."""
+    if points.dim() != 2:
+        raise ValueError("points must be an (n, dim) tensor")
+    n, dim = points.shape
+    dev = points.device
+    p = _as_dev(points, torch.float32, dev)
+    with torch.cuda.device(dev):
+        m = max(n - 1, 0)
+        u = torch.empty(m, dtype=torch.int32, device=dev)
+        v = torch.empty(m, dtype=torch.int32, device=dev)
+        w64 = torch.empty(m, dtype=torch.float64, device=dev)
+        w32 = torch.empty(m, dtype=torch.float32, device=dev)
+        _check(_load().pandora_emst(int(n), int(dim), _dptr(p), int(min_pts), _dptr(u), _dptr(v), _dptr(w64),
+                                    _dptr(w32), _stream_handle(stream)))
+    return u, v, w64, w32
+
+
+def hdbscan(points: torch.Tensor, min_pts: int, min_cluster_size: int, stream=None):
+    """HDBSCAN* end to end on the GPU: the mutual-reachability MST, its
+    dendrogram and the excess-of-mass flat clusters.  Returns (labels[n],
+    stability[k]) as device tensors (labels numbered by smallest point index,
+    -1 = noise)."""
+    u, v, _, w32 = emst(points, min_pts, stream=stream)
+    labels, stab, _, _ = flat_clusters(u, v, w32, min_cluster_size, n=points.shape[0], stream=stream)
+    return labels, stab
 
 
 def flat_clusters_workspace_bytes(n: int) -> int:

@@ -263,6 +263,36 @@ hipError_t launch_fc_tree(FlatArgs& a, int rounds, hipStream_t s);  // heavy pat
 hipError_t launch_fc_eval(const FlatArgs& a, int round, hipStream_t s);
 hipError_t launch_fc_label(const FlatArgs& a, int rounds, hipStream_t s);
 
+// ---- mutual-reachability MST of a point cloud (HDBSCAN*'s first step) ---------------
+constexpr int kEmstMaxDim = 4;
+constexpr int kEmstMaxMinPts = 32;
+struct EmstArgs {
+    int64_t n;
+    int dim, min_pts;
+    const float* pts;          // [n * dim], row-major
+    double* core2;             // [n] squared core distances
+    int32_t* comp;             // [n] component (its root point)
+    int32_t* comp2;            // [n] next round's components
+    double* best_w;            // [n] least outgoing mrd2 of each point
+    int32_t* best_j;           // [n] its other endpoint (-1: none)
+    uint64_t* cmin_w;          // [n] per component root: least mrd2 (bits)
+    uint64_t* cmin_e;          // [n] per component root: least (lo << 32 | hi) at that weight
+    int32_t* parent[2];        // [n] hooking and pointer jumping
+    uint64_t* ew;              // [pow2 >= n-1] tree edges: mrd2 bits, endpoints
+    int32_t* ea;
+    int32_t* eb;
+    int32_t* u;                // [n-1] outputs, in (mrd2, u, v) order, u < v
+    int32_t* v;
+    double* w64;               // may be null
+    float* w32;
+    uint32_t* counters;        // [4] edges, components, error bits, pointer-jumping changes
+};
+hipError_t launch_em_core(const EmstArgs& a, hipStream_t s);
+hipError_t launch_em_round(const EmstArgs& a, hipStream_t s);
+hipError_t launch_em_jump(const EmstArgs& a, int src, hipStream_t s);
+hipError_t launch_em_relabel(const EmstArgs& a, int src, hipStream_t s);
+hipError_t launch_em_sort_out(const EmstArgs& a, int64_t len, hipStream_t s);
+
 // ---- misc -----------------------------------------------------------------------
 // Clears the control block; voff1, if given, receives the offsets {0, n} of a
 // single tree.

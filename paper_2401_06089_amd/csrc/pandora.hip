@@ -1006,6 +1006,102 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
     return PANDORA_OK;
 }
 
+// ---- mutual-reachability MST of a point cloud -------------------------------------
+
+struct EmstLayout {
+    size_t core2, comp, comp2, best_w, best_j, cmin_w, cmin_e, par0, par1, ew, ea, eb, counters;
+    int64_t len = 0;   // padded edge-list length (a power of two >= n - 1)
+    size_t total = 0;
+};
+
+EmstLayout make_emst_layout(int64_t n) {
+    EmstLayout E;
+    E.len = 1;
+    while (E.len < n - 1) E.len <<= 1;
+    size_t c = 0;
+    E.core2 = take(c, 8 * n);
+    E.comp = take(c, 4 * n);
+    E.comp2 = take(c, 4 * n);
+    E.best_w = take(c, 8 * n);
+    E.best_j = take(c, 4 * n);
+    E.cmin_w = take(c, 8 * n);
+    E.cmin_e = take(c, 8 * n);
+    E.par0 = take(c, 4 * n);
+    E.par1 = take(c, 4 * n);
+    E.ew = take(c, 8 * E.len);
+    E.ea = take(c, 4 * E.len);
+    E.eb = take(c, 4 * E.len);
+    E.counters = take(c, 16);
+    E.total = c;
+    return E;
+}
+
+// Synchronous: Borůvka rounds until one component, then the sorted tree.
+int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32_t* u, int32_t* v, double* w64,
+             float* w32, hipStream_t s) {
+    if (n == 1) return PANDORA_OK;
+    int dev = 0;
+    PD_TRY(hipGetDevice(&dev));
+    Workspace& ws = *workspace_for(dev, s);
+    std::lock_guard<std::mutex> lock(ws.mu);
+    const EmstLayout E = make_emst_layout(n);
+    int rc = ensure(ws, E.total, host_bytes_for(1));
+    if (rc != PANDORA_OK) return rc;
+    void* d = ws.dev;
+    EmstArgs a{};
+    a.n = n;
+    a.dim = dim;
+    a.min_pts = min_pts;
+    a.pts = points;
+    a.core2 = at<double>(d, E.core2);
+    a.comp = at<int32_t>(d, E.comp);
+    a.comp2 = at<int32_t>(d, E.comp2);
+    a.best_w = at<double>(d, E.best_w);
+    a.best_j = at<int32_t>(d, E.best_j);
+    a.cmin_w = at<uint64_t>(d, E.cmin_w);
+    a.cmin_e = at<uint64_t>(d, E.cmin_e);
+    a.parent[0] = at<int32_t>(d, E.par0);
+    a.parent[1] = at<int32_t>(d, E.par1);
+    a.ew = at<uint64_t>(d, E.ew);
+    a.ea = at<int32_t>(d, E.ea);
+    a.eb = at<int32_t>(d, E.eb);
+    a.u = u;
+    a.v = v;
+    a.w64 = w64;
+    a.w32 = w32;
+    a.counters = at<uint32_t>(d, E.counters);
+    uint32_t* hc = static_cast<uint32_t*>(ws.host);       // pinned readback of the counters
+    PD_TRY(launch_clear_words(a.counters, 4, s));
+    PD_TRY(launch_em_core(a, s));
+    int64_t comps = n;
+    for (int round = 0; comps > 1; ++round) {
+        if (round > 64) return PANDORA_ERR_HIP;           // every round at least halves the components
+        PD_TRY(launch_em_round(a, s));
+        int src = 0;
+        for (int jr = 0;; ++jr) {
+            if (jr > 64) return PANDORA_ERR_HIP;
+            PD_TRY(launch_clear_words(a.counters + 3, 1, s));
+            PD_TRY(launch_em_jump(a, src, s));
+            src ^= 1;
+            PD_TRY(hipMemcpyAsync(hc, a.counters, 16, hipMemcpyDeviceToHost, s));
+            PD_TRY(hipStreamSynchronize(s));
+            if (hc[2]) return (hc[2] & 1u) ? PANDORA_ERR_INVALID_ARG : PANDORA_ERR_HIP;
+            if (hc[3] == 0) break;
+        }
+        PD_TRY(launch_clear_words(a.counters + 1, 1, s));
+        PD_TRY(launch_em_relabel(a, src, s));
+        PD_TRY(hipMemcpyAsync(hc, a.counters, 16, hipMemcpyDeviceToHost, s));
+        PD_TRY(hipStreamSynchronize(s));
+        if (hc[2]) return PANDORA_ERR_HIP;
+        if ((int64_t)hc[1] >= comps) return PANDORA_ERR_HIP;   // no progress: cannot happen
+        comps = hc[1];
+    }
+    if ((int64_t)hc[0] != n - 1) return PANDORA_ERR_HIP;
+    PD_TRY(launch_em_sort_out(a, E.len, s));
+    PD_TRY(hipStreamSynchronize(s));
+    return PANDORA_OK;
+}
+
 }  // namespace
 }  // namespace pandora
 
@@ -1100,6 +1196,15 @@ int pandora_flat_clusters(int64_t n, const int32_t* u, const int32_t* v, const f
         drain_profile();
     }
     return rc;
+}
+
+int pandora_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32_t* u, int32_t* v, double* w64,
+                 float* w32, void* hip_stream) {
+    if (n < 1 || n > (int64_t(1) << 24) || dim < 1 || dim > kEmstMaxDim || min_pts < 1 ||
+        min_pts > kEmstMaxMinPts || min_pts > n || !points)
+        return PANDORA_ERR_INVALID_ARG;
+    if (n > 1 && (!u || !v || !w32)) return PANDORA_ERR_INVALID_ARG;
+    return run_emst(n, dim, points, min_pts, u, v, w64, w32, static_cast<hipStream_t>(hip_stream));
 }
 
 size_t pandora_flat_clusters_workspace_bytes(int64_t n) {

@@ -45,6 +45,7 @@ def lib():
     L.pandora_set_workspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     L.pandora_flat_clusters.argtypes = ([ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int32]
                                         + [ctypes.c_void_p] * 6)
+    L.pandora_emst.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 5
     L.pandora_flat_clusters_workspace_bytes.restype = ctypes.c_size_t
     L.pandora_flat_clusters_workspace_bytes.argtypes = [ctypes.c_int64]
     yield L
@@ -62,9 +63,10 @@ def test_header_declares_the_api():
                  "pandora_graph_create", "pandora_graph_launch", "pandora_set_tuning"):
         assert must in names
     for must in ("pandora_dendrogram_async", "pandora_dendrogram_batched_async", "pandora_stream_status",
-                 "pandora_set_workspace", "pandora_flat_clusters", "pandora_flat_clusters_workspace_bytes"):
+                 "pandora_set_workspace", "pandora_flat_clusters", "pandora_flat_clusters_workspace_bytes",
+                 "pandora_emst"):
         assert must in names
-    assert len(names) == 22
+    assert len(names) == 23
 
 
 def test_library_exports_exactly_the_declared_functions(lib):
@@ -133,6 +135,16 @@ def test_argument_errors_come_back_before_any_launch(lib):
     assert lib.pandora_flat_clusters(10, d, d, d, 5, None, d, d, None, kp, None) == INVALID_ARG
     assert lib.pandora_flat_clusters(1_200_000_000, d, d, d, 5, d, d, d, None, kp, None) == INVALID_ARG
     assert k.value == -1
+    # point clouds: sizes, dimension, min_pts and required pointers
+    assert lib.pandora_emst(0, 2, d, 2, d, d, None, d, None) == INVALID_ARG
+    assert lib.pandora_emst(10, 0, d, 2, d, d, None, d, None) == INVALID_ARG
+    assert lib.pandora_emst(10, 5, d, 2, d, d, None, d, None) == INVALID_ARG
+    assert lib.pandora_emst(10, 2, d, 0, d, d, None, d, None) == INVALID_ARG
+    assert lib.pandora_emst(10, 2, d, 11, d, d, None, d, None) == INVALID_ARG   # more than n
+    assert lib.pandora_emst(100, 2, d, 33, d, d, None, d, None) == INVALID_ARG
+    assert lib.pandora_emst(10, 2, None, 2, d, d, None, d, None) == INVALID_ARG
+    assert lib.pandora_emst(10, 2, d, 2, d, d, None, None, None) == INVALID_ARG
+    assert lib.pandora_emst((1 << 24) + 1, 2, d, 2, d, d, None, d, None) == INVALID_ARG
 
 
 def test_tuning_validation_and_thread_scope(lib):

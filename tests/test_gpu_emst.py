@@ -1,0 +1,80 @@
+"""Mutual-reachability MST of point clouds on the GPU against the oracle: the
+same edges in the same order with bit-equal fp64 and fp32 weights, for every
+dimension and min_pts, ties included (coarse grids); and HDBSCAN* end to end
+(points -> MST -> dendrogram -> flat clusters) against the oracle chain."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.emst import emst as oracle_emst
+from oracle.flat_clusters import decisions_safe, flat_clusters as oracle_flat
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2401_06089_amd as pd
+    pd.library()
+    yield
+
+
+def cloud(n, dim, seed, kind):
+    rng = np.random.default_rng(seed)
+    if kind == "normal":
+        return rng.normal(0, 1, (n, dim)).astype(np.float32)
+    if kind == "blobs":
+        centers = rng.uniform(-30, 30, (8, dim))
+        return (centers[rng.integers(0, 8, n)] + rng.normal(0, 1.5, (n, dim))).astype(np.float32)
+    if kind == "grid":                        # many equal distances: ties decided by the ids
+        return (np.round(rng.uniform(0, 12, (n, dim))) / 2).astype(np.float32)
+    return rng.uniform(0, 1, (n, dim)).astype(np.float32)
+
+
+def check(x, min_pts):
+    import paper_2401_06089_amd as pd
+    print(f"emst n={len(x)} dim={x.shape[1]} min_pts={min_pts}", flush=True)
+    u, v, w64, w32 = pd.emst(torch.from_numpy(x).cuda(), min_pts)
+    ou, ov, ow64, ow32, _ = oracle_emst(x, min_pts)
+    assert np.array_equal(u.cpu().numpy(), ou) and np.array_equal(v.cpu().numpy(), ov)
+    assert np.array_equal(w64.cpu().numpy(), ow64) and np.array_equal(w32.cpu().numpy(), ow32)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3, 4])
+@pytest.mark.parametrize("min_pts", [1, 2, 5, 32])
+def test_matches_oracle(dim, min_pts):
+    check(cloud(1500, dim, 10 * dim + min_pts, "blobs"), min_pts)
+
+
+@pytest.mark.parametrize("kind", ["normal", "uniform", "grid"])
+def test_shapes_and_ties(kind):
+    for n, mp in ((2, 1), (2, 2), (3, 3), (257, 4), (3000, 8)):
+        check(cloud(n, 3, n + mp, kind), mp)
+
+
+def test_single_point_and_errors():
+    import paper_2401_06089_amd as pd
+    u, v, w64, w32 = pd.emst(torch.zeros((1, 2), dtype=torch.float32, device="cuda"), 1)
+    assert u.numel() == 0
+    x = cloud(100, 2, 1, "normal")
+    x[7, 1] = np.float32("nan")
+    with pytest.raises(pd.PandoraError) as ei:
+        pd.emst(torch.from_numpy(x).cuda(), 3)
+    assert ei.value.status == pd.INVALID_ARG
+    with pytest.raises(pd.PandoraError):
+        pd.emst(torch.zeros((10, 5), dtype=torch.float32, device="cuda"), 2)
+    check(cloud(500, 2, 2, "normal"), 3)      # the stream's workspace is fine afterwards
+
+
+@pytest.mark.parametrize("seed,min_pts,mcs", [(1, 2, 10), (2, 4, 20), (3, 8, 40)])
+def test_hdbscan_end_to_end(seed, min_pts, mcs):
+    import paper_2401_06089_amd as pd
+    x = cloud(4000, 2 + seed % 2, seed, "blobs")
+    lab, st = pd.hdbscan(torch.from_numpy(x).cuda(), min_pts, mcs)
+    ou, ov, _, ow32, _ = oracle_emst(x, min_pts)
+    olab, ost, info = oracle_flat(len(x), ou, ov, ow32, mcs, return_info=True)
+    assert decisions_safe(info)
+    assert np.array_equal(lab.cpu().numpy(), olab)
+    assert st.numel() == ost.size >= 2
