@@ -29,7 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FLAT_MCS = 100   # minimum cluster size of the flat-cluster workload
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FLAT_MCS = 100   # minimum cluster size of the flat-cluster workloads
+HDB_POINTS, HDB_DIM, HDB_MIN_PTS = 200_000, 3, 2
 
 WORKLOADS = {
     "c2": "two single trees, n=10,000,000 each: (a) random recursive tree, fp32 uniform [0,1) "
@@ -41,6 +43,8 @@ WORKLOADS = {
     "c3": "preferential-attachment tree, n=50,000,000, lognormal(0,1.5) fp32 weights, 5% x10 bridges",
     "c3flat": "HDBSCAN* flat clusters (min cluster size 100) of the preferential-attachment tree, "
               "n=50,000,000, lognormal(0,1.5) fp32 weights, 5% x10 bridges: dendrogram + clusters per call",
+    "hdb3d": "HDBSCAN* end to end on 200,000 uniform points in the unit cube (3D), min_pts 2, min cluster "
+             "size 100: mutual-reachability MST (brute force), dendrogram and flat clusters per call",
     "c4": "4,096 trees, lognormal sizes in [100, 1,000,000] (~50M edges), half random-recursive "
           "half caterpillar, fp32 uniform weights, one batched call",
     "c5": "serving: Poisson arrivals at 2,000 req/s of random recursive trees with log-uniform "
@@ -189,6 +193,8 @@ def main():
 
     if args.workload == "c5":
         return run_serving(args, dev)
+    if args.workload == "hdb3d":
+        return run_points(args, dev)
 
     t0 = time.time()
     items = make_inputs(args.workload)
@@ -438,6 +444,79 @@ def main():
                                          f"single-threaded sort + union-find sweep",
                                "seconds": cpu_s, "host_cpu": cpu_model(),
                                "host_threads_available": os.cpu_count()}
+    print(json.dumps(out), flush=True)
+
+
+def uniform_points(n, dim, seed):
+    import numpy as np
+    import gen
+    return gen.uniform_f64(n * dim, seed, 21).reshape(n, dim).astype(np.float32)
+
+
+def run_points(args, dev):
+    """HDBSCAN* on a point cloud: MST, dendrogram and flat clusters per step."""
+    import numpy as np
+    import torch
+
+    import paper_2401_06089_amd as pd
+
+    pts = torch.from_numpy(uniform_points(HDB_POINTS, HDB_DIM, 0)).to(dev)
+    torch.cuda.synchronize()
+    ks = []
+
+    def step():
+        lab, st = pd.hdbscan(pts, HDB_MIN_PTS, FLAT_MCS)
+        ks.append(st.numel())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    pd.profile_enable(pd.PROFILE_ALL)
+    step()
+    torch.cuda.synchronize()
+    stages = pd.profile_read()
+    pd.profile_enable(0)
+    lat = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1000.0 * elapsed / args.steps
+    search = stages["emst_search"]
+    achieved = search["bytes"] / (search["ms"] / 1000.0) / 1e12 if search["ms"] > 0 else 0.0
+    out = {
+        "metric": "HDBSCAN* points/sec (mutual-reachability MST + dendrogram + flat clusters)",
+        "value": HDB_POINTS * args.steps / elapsed,
+        "unit": "points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "hdb3d", "description": WORKLOADS["hdb3d"], "points": HDB_POINTS, "dim": HDB_DIM,
+                   "min_pts": HDB_MIN_PTS, "min_cluster_size": FLAT_MCS, "clusters": ks[-1] if ks else None,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": 1000 * statistics.median(lat), "p99": 1000 * float(np.percentile(lat, 99)),
+                       "per": "step"},
+        "roofline": {"bound": "alu", "kernel": "emst_search", "achieved": achieved,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "ops": "fp64 operations of the point-pair sweeps (3 per coordinate + 2)",
+                     "launches": search["launches"]},
+        "stages": {k: {"ms": v["ms"], "launches": v["launches"]} for k, v in stages.items() if v["launches"]},
+    }
+    if not args.no_cpu_baseline:
+        from oracle.emst import emst as oracle_emst
+        from oracle.flat_clusters import flat_clusters as oracle_flat
+        sample = uniform_points(4000, HDB_DIM, 0)
+        log("timing the CPU oracle on a 4,000-point sample ...")
+        t1 = time.perf_counter()
+        u, v, _, w32, _ = oracle_emst(sample, HDB_MIN_PTS)
+        oracle_flat(len(sample), u, v, w32, FLAT_MCS)
+        cpu_s = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": len(sample) / cpu_s, "unit": "points/s", "cores": 1, "kind": "oracle",
+                               "sample": "4,000 points of the same generator (the oracle is O(n^2), so its rate "
+                                         "falls with n)",
+                               "seconds": cpu_s, "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
     print(json.dumps(out), flush=True)
 
 

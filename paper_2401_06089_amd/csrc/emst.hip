@@ -12,7 +12,8 @@
 //
 // Borůvka rounds: every point finds its least edge to another component by a
 // brute-force sweep over LDS tiles of all points (dense fp64 vector work,
-// no matrix core shape), components take the least edge of their points
+// no matrix core shape); a point whose previous least edge still leaves its
+// component keeps it.  Components take the least edge of their points
 // (two atomic minima: weight bits, then endpoints), hook along it (a
 // mutual pair keeps the smaller root), and pointer jumping relabels.  Each
 // round at least halves the components.  The tree's edges are then sorted
@@ -95,18 +96,37 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a) {
             if (t == K - 1) c = top[t];
         a.core2[i] = c;
         a.comp[i] = (int32_t)i;
+        a.best_j[i] = -1;
         a.cmin_w[i] = ~0ull;
         a.cmin_e[i] = ~0ull;
     }
     if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&a.counters[2], 1u);
 }
 
-// Every point's least edge to another component.
-__global__ __launch_bounds__(kEmBlock) void k_em_best(EmstArgs a) {
+// A point's least edge to another component stays its least edge while its
+// other end is still outside the point's (grown) component: the candidates
+// only lose points.  Such points report it at once; the others are listed
+// for a new search.
+__global__ void k_em_active(EmstArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int32_t j = a.best_j[i];
+    const int32_t mc = a.comp[i];
+    if (j >= 0 && a.comp[j] != mc) {
+        atomicMin((unsigned long long*)&a.cmin_w[mc], (unsigned long long)__double_as_longlong(a.best_w[i]));
+    } else {
+        const uint32_t k = atomicAdd(&a.counters[3], 1u);
+        a.active[k] = (int32_t)i;
+    }
+}
+
+// Every listed point's least edge to another component.
+__global__ __launch_bounds__(kEmBlock) void k_em_best(EmstArgs a, int64_t count) {
     __shared__ double s_p[kEmBlock][kEmstMaxDim];
     __shared__ double s_c[kEmBlock];
     __shared__ int32_t s_comp[kEmBlock];
-    const int64_t i = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
+    const int64_t slot = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
+    const int64_t i = slot < count ? a.active[slot] : a.n;
     double me[kEmstMaxDim];
 #pragma unroll
     for (int k = 0; k < kEmstMaxDim; ++k) me[k] = (i < a.n && k < a.dim) ? (double)a.pts[i * a.dim + k] : 0.0;
@@ -307,8 +327,13 @@ hipError_t launch_em_core(const EmstArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_em_round(const EmstArgs& a, hipStream_t s) {
-    k_em_best<<<em_blocks(a.n, kEmBlock), kEmBlock, 0, s>>>(a);
+hipError_t launch_em_active(const EmstArgs& a, hipStream_t s) {
+    k_em_active<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_round(const EmstArgs& a, int64_t active, hipStream_t s) {
+    if (active > 0) k_em_best<<<em_blocks(active, kEmBlock), kEmBlock, 0, s>>>(a, active);
     k_em_cmin<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
     k_em_hook<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
     return hipGetLastError();

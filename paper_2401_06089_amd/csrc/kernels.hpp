@@ -275,6 +275,7 @@ struct EmstArgs {
     int32_t* comp2;            // [n] next round's components
     double* best_w;            // [n] least outgoing mrd2 of each point
     int32_t* best_j;           // [n] its other endpoint (-1: none)
+    int32_t* active;           // [n] points that search again this round
     uint64_t* cmin_w;          // [n] per component root: least mrd2 (bits)
     uint64_t* cmin_e;          // [n] per component root: least (lo << 32 | hi) at that weight
     int32_t* parent[2];        // [n] hooking and pointer jumping
@@ -285,10 +286,11 @@ struct EmstArgs {
     int32_t* v;
     double* w64;               // may be null
     float* w32;
-    uint32_t* counters;        // [4] edges, components, error bits, pointer-jumping changes
+    uint32_t* counters;        // [4] edges, components, error bits, pointer-jumping changes / active points
 };
 hipError_t launch_em_core(const EmstArgs& a, hipStream_t s);
-hipError_t launch_em_round(const EmstArgs& a, hipStream_t s);
+hipError_t launch_em_active(const EmstArgs& a, hipStream_t s);   // counts into counters[3]
+hipError_t launch_em_round(const EmstArgs& a, int64_t active, hipStream_t s);
 hipError_t launch_em_jump(const EmstArgs& a, int src, hipStream_t s);
 hipError_t launch_em_relabel(const EmstArgs& a, int src, hipStream_t s);
 hipError_t launch_em_sort_out(const EmstArgs& a, int64_t len, hipStream_t s);

@@ -229,6 +229,7 @@ enum ProfKind {
     PK_OWN, PK_CLASSIFY, PK_JUMP, PK_COMPACT, PK_TAIL, PK_WALK_HIST, PK_SORT_C_PASS, PK_STITCH,
     PK_MIN_INC_N, PK_OWN_N, PK_CLASSIFY_N, PK_JUMP_N, PK_COMPACT_N, PK_LEVELS,
     PK_FC_PREPARE, PK_FC_SIZES, PK_FC_CLUSTERS, PK_FC_STAB, PK_FC_SELECT, PK_FC_LABEL,
+    PK_EM_CORE, PK_EM_SEARCH, PK_EM_MERGE, PK_EM_SORT,
     PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
@@ -236,7 +237,7 @@ const char* const kProfNames[PK_COUNT] = {
     "sort_pass_weight_last", "min_incident_l0", "own_l0", "classify_l0", "jump_l0", "compact_l0",
     "tail", "walk_hist", "sort_pass_chain", "stitch", "min_incident_ln", "own_ln", "classify_ln",
     "jump_ln", "compact_ln", "levels_persistent", "flat_prepare", "flat_sizes", "flat_clusters",
-    "flat_stability", "flat_select", "flat_label"};
+    "flat_stability", "flat_select", "flat_label", "emst_core", "emst_search", "emst_merge", "emst_sort"};
 
 struct Prof {
     std::mutex mu;
@@ -1009,7 +1010,7 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
 // ---- mutual-reachability MST of a point cloud -------------------------------------
 
 struct EmstLayout {
-    size_t core2, comp, comp2, best_w, best_j, cmin_w, cmin_e, par0, par1, ew, ea, eb, counters;
+    size_t core2, comp, comp2, best_w, best_j, active, cmin_w, cmin_e, par0, par1, ew, ea, eb, counters;
     int64_t len = 0;   // padded edge-list length (a power of two >= n - 1)
     size_t total = 0;
 };
@@ -1024,6 +1025,7 @@ EmstLayout make_emst_layout(int64_t n) {
     E.comp2 = take(c, 4 * n);
     E.best_w = take(c, 8 * n);
     E.best_j = take(c, 4 * n);
+    E.active = take(c, 4 * n);
     E.cmin_w = take(c, 8 * n);
     E.cmin_e = take(c, 8 * n);
     E.par0 = take(c, 4 * n);
@@ -1058,6 +1060,7 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
     a.comp2 = at<int32_t>(d, E.comp2);
     a.best_w = at<double>(d, E.best_w);
     a.best_j = at<int32_t>(d, E.best_j);
+    a.active = at<int32_t>(d, E.active);
     a.cmin_w = at<uint64_t>(d, E.cmin_w);
     a.cmin_e = at<uint64_t>(d, E.cmin_e);
     a.parent[0] = at<int32_t>(d, E.par0);
@@ -1071,17 +1074,26 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
     a.w32 = w32;
     a.counters = at<uint32_t>(d, E.counters);
     uint32_t* hc = static_cast<uint32_t*>(ws.host);       // pinned readback of the counters
+    // The searches are dense fp64 work: their "bytes" in the profiler are
+    // fp64 operations, 3 per coordinate and 2 more per point pair.
+    const double pair_ops = (double)n * (double)n * (3.0 * dim + 2.0);
     PD_TRY(launch_clear_words(a.counters, 4, s));
-    PD_TRY(launch_em_core(a, s));
+    PD_TIMED(PK_EM_CORE, pair_ops, launch_em_core(a, s));
     int64_t comps = n;
     for (int round = 0; comps > 1; ++round) {
         if (round > 64) return PANDORA_ERR_HIP;           // every round at least halves the components
-        PD_TRY(launch_em_round(a, s));
+        PD_TRY(launch_clear_words(a.counters + 3, 1, s));
+        PD_TRY(launch_em_active(a, s));
+        PD_TRY(hipMemcpyAsync(hc, a.counters, 16, hipMemcpyDeviceToHost, s));
+        PD_TRY(hipStreamSynchronize(s));
+        const int64_t active = hc[3];
+        if (active > n) return PANDORA_ERR_HIP;
+        PD_TIMED(PK_EM_SEARCH, (double)active * (double)n * (3.0 * dim + 2.0), launch_em_round(a, active, s));
         int src = 0;
         for (int jr = 0;; ++jr) {
             if (jr > 64) return PANDORA_ERR_HIP;
             PD_TRY(launch_clear_words(a.counters + 3, 1, s));
-            PD_TRY(launch_em_jump(a, src, s));
+            PD_TIMED(PK_EM_MERGE, 12.0 * (double)comps, launch_em_jump(a, src, s));
             src ^= 1;
             PD_TRY(hipMemcpyAsync(hc, a.counters, 16, hipMemcpyDeviceToHost, s));
             PD_TRY(hipStreamSynchronize(s));
@@ -1089,7 +1101,7 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
             if (hc[3] == 0) break;
         }
         PD_TRY(launch_clear_words(a.counters + 1, 1, s));
-        PD_TRY(launch_em_relabel(a, src, s));
+        PD_TIMED(PK_EM_MERGE, 40.0 * (double)n, launch_em_relabel(a, src, s));
         PD_TRY(hipMemcpyAsync(hc, a.counters, 16, hipMemcpyDeviceToHost, s));
         PD_TRY(hipStreamSynchronize(s));
         if (hc[2]) return PANDORA_ERR_HIP;
@@ -1097,7 +1109,7 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
         comps = hc[1];
     }
     if ((int64_t)hc[0] != n - 1) return PANDORA_ERR_HIP;
-    PD_TRY(launch_em_sort_out(a, E.len, s));
+    PD_TIMED(PK_EM_SORT, 32.0 * (double)E.len, launch_em_sort_out(a, E.len, s));
     PD_TRY(hipStreamSynchronize(s));
     return PANDORA_OK;
 }
@@ -1204,7 +1216,12 @@ int pandora_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, i
         min_pts > kEmstMaxMinPts || min_pts > n || !points)
         return PANDORA_ERR_INVALID_ARG;
     if (n > 1 && (!u || !v || !w32)) return PANDORA_ERR_INVALID_ARG;
-    return run_emst(n, dim, points, min_pts, u, v, w64, w32, static_cast<hipStream_t>(hip_stream));
+    const int rc = run_emst(n, dim, points, min_pts, u, v, w64, w32, static_cast<hipStream_t>(hip_stream));
+    if (!t_pending.empty()) {
+        (void)hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+        drain_profile();
+    }
+    return rc;
 }
 
 size_t pandora_flat_clusters_workspace_bytes(int64_t n) {
