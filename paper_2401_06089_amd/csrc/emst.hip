@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kEmBlock = 256;
 constexpr int kEmMaxK = kEmstMaxMinPts - 1;       // core-distance rank held in registers
+constexpr int kGridRingCap = 4;                    // rings searched in the grid before a full sweep
 
 __device__ __forceinline__ double d2_of(const double* a, const double* b, int dim) {
 #pragma clang fp contract(off)   // every product and sum rounded on its own, as defined
@@ -47,9 +48,12 @@ __device__ __forceinline__ bool key_less(double w, int32_t lo, int32_t hi, doubl
 
 // Core distances: each thread keeps the K smallest d2 of its point in
 // registers (sorted, fully unrolled so that nothing spills).
-__global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a) {
+// With a list, only the listed points (the grid search's leftovers), and
+// nothing but their core distance is written.
+__global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t* list, int64_t count) {
     __shared__ double s_p[kEmBlock][kEmstMaxDim];
-    const int64_t i = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
+    const int64_t slot = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
+    const int64_t i = list ? (slot < count ? list[slot] : a.n) : slot;
     const int K = a.min_pts - 1;
     double me[kEmstMaxDim];
     bool bad = false;
@@ -95,10 +99,12 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a) {
         for (int t = 0; t < kEmMaxK; ++t)
             if (t == K - 1) c = top[t];
         a.core2[i] = c;
-        a.comp[i] = (int32_t)i;
-        a.best_j[i] = -1;
-        a.cmin_w[i] = ~0ull;
-        a.cmin_e[i] = ~0ull;
+        if (!list) {
+            a.comp[i] = (int32_t)i;
+            a.best_j[i] = -1;
+            a.cmin_w[i] = ~0ull;
+            a.cmin_e[i] = ~0ull;
+        }
     }
     if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&a.counters[2], 1u);
 }
@@ -112,7 +118,7 @@ __global__ void k_em_active(EmstArgs a) {
     if (i >= a.n) return;
     const int32_t j = a.best_j[i];
     const int32_t mc = a.comp[i];
-    if (j >= 0 && a.comp[j] != mc) {
+    if (j >= 0 && a.comp[j] != mc && !(a.use_grid && a.partial[i])) {
         atomicMin((unsigned long long*)&a.cmin_w[mc], (unsigned long long)__double_as_longlong(a.best_w[i]));
     } else {
         const uint32_t k = atomicAdd(&a.counters[3], 1u);
@@ -121,12 +127,12 @@ __global__ void k_em_active(EmstArgs a) {
 }
 
 // Every listed point's least edge to another component.
-__global__ __launch_bounds__(kEmBlock) void k_em_best(EmstArgs a, int64_t count) {
+__global__ __launch_bounds__(kEmBlock) void k_em_best(EmstArgs a, const int32_t* list, int64_t count) {
     __shared__ double s_p[kEmBlock][kEmstMaxDim];
     __shared__ double s_c[kEmBlock];
     __shared__ int32_t s_comp[kEmBlock];
     const int64_t slot = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
-    const int64_t i = slot < count ? a.active[slot] : a.n;
+    const int64_t i = slot < count ? list[slot] : a.n;
     double me[kEmstMaxDim];
 #pragma unroll
     for (int k = 0; k < kEmstMaxDim; ++k) me[k] = (i < a.n && k < a.dim) ? (double)a.pts[i * a.dim + k] : 0.0;
@@ -318,12 +324,325 @@ __global__ void k_em_out(EmstArgs a) {
     a.w32[k] = __double2float_rn(w);
 }
 
+// ---- uniform grid ------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t order_bits(float f) {      // monotone in f
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__global__ void k_em_bbox(EmstArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t lo[kEmstMaxDim], hi[kEmstMaxDim];
+#pragma unroll
+    for (int k = 0; k < kEmstMaxDim; ++k) {
+        lo[k] = 0xffffffffu;
+        hi[k] = 0u;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+#pragma unroll
+        for (int k = 0; k < kEmstMaxDim; ++k) {
+            if (k < a.dim) {
+                const uint32_t b = order_bits(a.pts[i * a.dim + k]);
+                lo[k] = lo[k] < b ? lo[k] : b;
+                hi[k] = hi[k] > b ? hi[k] : b;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kEmstMaxDim; ++k) {
+        if (k < a.dim) {
+            atomicMin(&a.bbox[2 * k], lo[k]);
+            atomicMin(&a.bbox[2 * k + 1], ~hi[k]);         // the maximum, complemented
+        }
+    }
+}
+
+// Cell coordinate of x along dimension k (clamped: the floor of a rounded
+// quotient may land one cell off, which the search bounds allow for).
+__device__ __forceinline__ int32_t cell_coord(const EmstArgs& a, double x, int k) {
+    const double q = floor((x - a.gmin[k]) * a.inv_h);
+    const double c = q < 0.0 ? 0.0 : (q > (double)(a.gdim[k] - 1) ? (double)(a.gdim[k] - 1) : q);
+    return (int32_t)c;
+}
+
+__global__ void k_em_cells(EmstArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    int64_t cell = 0;
+    for (int k = 0; k < a.dim; ++k) cell += (int64_t)cell_coord(a, (double)a.pts[i * a.dim + k], k) * a.gstride[k];
+    a.cellof[i] = (int32_t)cell;
+    atomicAdd(&a.cfill[cell], 1);
+}
+
+// Exclusive scan of the cell counts into cstart (block sums, one block over
+// the sums, then the block offsets); cfill is cleared for the scatter.
+constexpr int kScanB = 1024, kScanI = 4;
+__device__ uint64_t em_block_excl(uint64_t x, uint64_t* s_w, uint64_t* total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    uint64_t inc = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += y;
+    }
+    if (lane == kWave - 1) s_w[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t run = 0;
+        for (int w = 0; w < kScanB / kWave; ++w) {
+            const uint64_t t = s_w[w];
+            s_w[w] = run;
+            run += t;
+        }
+        s_w[kScanB / kWave] = run;
+    }
+    __syncthreads();
+    const uint64_t res = s_w[wave] + inc - x;
+    *total = s_w[kScanB / kWave];
+    __syncthreads();
+    return res;
+}
+
+__global__ __launch_bounds__(kScanB) void k_em_scan1(EmstArgs a) {
+    __shared__ uint64_t s_w[kScanB / kWave + 1];
+    const int64_t base = ((int64_t)blockIdx.x * kScanB + threadIdx.x) * kScanI;
+    uint64_t v = 0;
+    for (int j = 0; j < kScanI; ++j)
+        if (base + j < a.ncells) v += (uint64_t)a.cfill[base + j];
+    uint64_t total;
+    (void)em_block_excl(v, s_w, &total);
+    if (threadIdx.x == 0) a.scan_agg[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanB) void k_em_scan2(EmstArgs a, int64_t blocks) {
+    __shared__ uint64_t s_w[kScanB / kWave + 1];
+    uint64_t run = 0;
+    for (int64_t c0 = 0; c0 < blocks; c0 += kScanB) {
+        const int64_t t = c0 + threadIdx.x;
+        const uint64_t x = t < blocks ? a.scan_agg[t] : 0;
+        uint64_t total;
+        const uint64_t ex = em_block_excl(x, s_w, &total);
+        if (t < blocks) a.scan_agg[t] = run + ex;
+        run += total;
+    }
+    if (threadIdx.x == 0) a.cstart[a.ncells] = (int32_t)a.n;
+}
+
+__global__ __launch_bounds__(kScanB) void k_em_scan3(EmstArgs a) {
+    __shared__ uint64_t s_w[kScanB / kWave + 1];
+    const int64_t base = ((int64_t)blockIdx.x * kScanB + threadIdx.x) * kScanI;
+    int32_t c[kScanI];
+    uint64_t v = 0;
+    for (int j = 0; j < kScanI; ++j) {
+        c[j] = base + j < a.ncells ? a.cfill[base + j] : 0;
+        v += (uint64_t)c[j];
+    }
+    uint64_t total;
+    uint64_t run = a.scan_agg[blockIdx.x] + em_block_excl(v, s_w, &total);
+    for (int j = 0; j < kScanI; ++j) {
+        if (base + j >= a.ncells) break;
+        a.cstart[base + j] = (int32_t)run;
+        a.cfill[base + j] = 0;
+        run += (uint64_t)c[j];
+    }
+}
+
+// Points in cell order (the order inside a cell does not matter: every
+// search takes the least key under the total order).
+__global__ void k_em_scatter(EmstArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int32_t cell = a.cellof[i];
+    const int64_t pos = (int64_t)a.cstart[cell] + atomicAdd(&a.cfill[cell], 1);
+    a.sorted[pos] = (int32_t)i;
+#pragma unroll
+    for (int k = 0; k < kEmstMaxDim; ++k) a.spts[pos * kEmstMaxDim + k] = k < a.dim ? (double)a.pts[i * a.dim + k] : 0.0;
+}
+
+// Visits the cells of Chebyshev ring r around cell coordinates c (only cells
+// inside the grid); f(first, last) gets each cell's sorted positions.
+template <class F>
+__device__ __forceinline__ void for_ring(const EmstArgs& a, const int32_t* c, int r, F&& f) {
+    const int side = 2 * r + 1;
+    int64_t combos = 1;
+    for (int k = 0; k < a.dim; ++k) combos *= side;
+    for (int64_t t = 0; t < combos; ++t) {
+        int64_t rest = t, cell = 0;
+        bool inside = true, shell = false;
+        for (int k = 0; k < a.dim; ++k) {
+            const int d = (int)(rest % side) - r;
+            rest /= side;
+            shell |= (d == r || d == -r);
+            const int64_t ck = (int64_t)c[k] + d;
+            inside &= ck >= 0 && ck < a.gdim[k];
+            cell += ck * a.gstride[k];
+        }
+        if (!inside || !(shell || r == 0)) continue;
+        f(a.cstart[cell], a.cstart[cell + 1]);
+    }
+}
+
+// A point of a cell R rings away is at least R - 1 cell edges away, less
+// the few rounding units by which a rounded floor can misplace a point at a
+// cell boundary (gslack, from the coordinate magnitudes); the square is
+// shrunk once more against its own rounding.
+__device__ __forceinline__ double ring_bound2(const EmstArgs& a, int r) {
+    if (r < 1) return 0.0;
+    const double lb = (double)(r - 1) * a.h - a.gslack;
+    return lb > 0.0 ? lb * lb * (1.0 - 1e-12) : 0.0;
+}
+
+__device__ __forceinline__ int max_ring(const EmstArgs& a) {
+    int m = 0;
+    for (int k = 0; k < a.dim; ++k) m = a.gdim[k] > m ? a.gdim[k] : m;
+    return m;
+}
+
+// Core distances by widening rings: stop once the K-th smallest is no more
+// than the bound for everything farther out.
+__global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
+    if (i >= a.n) return;
+    const int K = a.min_pts - 1;
+    double me[kEmstMaxDim];
+    int32_t c[kEmstMaxDim];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kEmstMaxDim; ++k) {
+        me[k] = 0.0;
+        c[k] = 0;
+        if (k < a.dim) {
+            const float f = a.pts[i * a.dim + k];
+            bad |= !isfinite(f);
+            me[k] = (double)f;
+            c[k] = cell_coord(a, me[k], k);
+        }
+    }
+    if (bad) atomicOr(&a.counters[2], 1u);
+    double top[kEmMaxK];
+#pragma unroll
+    for (int t = 0; t < kEmMaxK; ++t) top[t] = INFINITY;
+    double thr = INFINITY;
+    bool done = K == 0;
+    if (K > 0) {
+        const int rmax = max_ring(a);
+        const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
+        for (int r = 0; r <= rcap; ++r) {
+            for_ring(a, c, r, [&](int32_t p0, int32_t p1) {
+                for (int32_t p = p0; p < p1; ++p) {
+                    if (a.sorted[p] == (int32_t)i) continue;
+                    const double d = d2_of(me, a.spts + (int64_t)p * kEmstMaxDim, a.dim);
+                    if (d >= thr) continue;
+#pragma unroll
+                    for (int t = kEmMaxK - 1; t >= 1; --t) top[t] = fmin(top[t], fmax(top[t - 1], d));
+                    top[0] = fmin(top[0], d);
+#pragma unroll
+                    for (int t = 0; t < kEmMaxK; ++t)
+                        if (t == K - 1) thr = top[t];
+                }
+            });
+            if (thr <= ring_bound2(a, r + 1) || r == rmax) {
+                done = true;
+                break;
+            }
+        }
+    }
+    if (!done) {                                          // far from its neighbours: full sweep later
+        const uint32_t k = atomicAdd(&a.counters[4], 1u);
+        a.fallback[k] = (int32_t)i;
+    }
+    double core = 0.0;
+#pragma unroll
+    for (int t = 0; t < kEmMaxK; ++t)
+        if (t == K - 1) core = top[t];
+    a.core2[i] = core;
+    a.comp[i] = (int32_t)i;
+    a.best_j[i] = -1;
+    a.partial[i] = 0;
+    a.cmin_w[i] = ~0ull;
+    a.cmin_e[i] = ~0ull;
+}
+
+__global__ void k_em_sorted_state(EmstArgs a, int with_core) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int32_t j = a.sorted[p];
+    a.scomp[p] = a.comp[j];
+    if (with_core) a.score2[p] = a.core2[j];
+}
+
+// Least edge to another component by widening rings.  The search ends when
+// nothing farther out can beat the best so far (complete), or when nothing
+// farther out can beat the least edge some point of the same component has
+// already reported (then this point cannot hold the component's least edge;
+// it searches again next round).
+__global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t count) {
+    const int64_t slot = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
+    if (slot >= count) return;
+    const int32_t i = a.active[slot];
+    double me[kEmstMaxDim];
+    int32_t c[kEmstMaxDim];
+#pragma unroll
+    for (int k = 0; k < kEmstMaxDim; ++k) {
+        me[k] = k < a.dim ? (double)a.pts[(int64_t)i * a.dim + k] : 0.0;
+        c[k] = k < a.dim ? cell_coord(a, me[k], k) : 0;
+    }
+    const double ci = a.core2[i];
+    const int32_t mc = a.comp[i];
+    double bw = INFINITY;
+    int32_t blo = INT32_MAX, bhi = INT32_MAX, bj = -1;
+    bool partial = false, done = false;
+    const int rmax = max_ring(a);
+    const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
+    for (int r = 0; r <= rcap; ++r) {
+        for_ring(a, c, r, [&](int32_t p0, int32_t p1) {
+            for (int32_t p = p0; p < p1; ++p) {
+                if (a.scomp[p] == mc) continue;
+                const double d = d2_of(me, a.spts + (int64_t)p * kEmstMaxDim, a.dim);
+                const double w = fmax(fmax(ci, a.score2[p]), d);
+                if (w > bw) continue;
+                const int32_t j = a.sorted[p];
+                const int32_t lo = j < i ? j : i, hi = j < i ? i : j;
+                if (key_less(w, lo, hi, bw, blo, bhi)) {
+                    bw = w;
+                    blo = lo;
+                    bhi = hi;
+                    bj = j;
+                }
+            }
+        });
+        const double lb2 = ring_bound2(a, r + 1);
+        if (bw < lb2 || r == rmax) {                          // complete
+            done = true;
+            break;
+        }
+        const uint64_t cb = __hip_atomic_load(&a.cmin_w[mc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cb != ~0ull && lb2 > __longlong_as_double((long long)cb)) {
+            partial = true;                                   // stopped early
+            done = true;
+            break;
+        }
+    }
+    if (!done) {                                          // far from other components: full sweep
+        a.partial[i] = 0;
+        const uint32_t k = atomicAdd(&a.counters[4], 1u);
+        a.fallback[k] = i;
+        return;
+    }
+    a.best_w[i] = bw;
+    a.best_j[i] = bj;
+    a.partial[i] = partial ? 1 : 0;
+    if (bj >= 0) atomicMin((unsigned long long*)&a.cmin_w[mc], (unsigned long long)__double_as_longlong(bw));
+}
+
 inline unsigned em_blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
 
-hipError_t launch_em_core(const EmstArgs& a, hipStream_t s) {
-    k_em_core<<<em_blocks(a.n, kEmBlock), kEmBlock, 0, s>>>(a);
+hipError_t launch_em_core(const EmstArgs& a, const int32_t* list, int64_t count, hipStream_t s) {
+    const int64_t m = list ? count : a.n;
+    if (m > 0) k_em_core<<<em_blocks(m, kEmBlock), kEmBlock, 0, s>>>(a, list, count);
     return hipGetLastError();
 }
 
@@ -332,10 +651,44 @@ hipError_t launch_em_active(const EmstArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_em_round(const EmstArgs& a, int64_t active, hipStream_t s) {
-    if (active > 0) k_em_best<<<em_blocks(active, kEmBlock), kEmBlock, 0, s>>>(a, active);
+hipError_t launch_em_search(const EmstArgs& a, const int32_t* list, int64_t count, hipStream_t s) {
+    if (count > 0) k_em_best<<<em_blocks(count, kEmBlock), kEmBlock, 0, s>>>(a, list, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_merge_edges(const EmstArgs& a, hipStream_t s) {
     k_em_cmin<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
     k_em_hook<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_bbox(const EmstArgs& a, hipStream_t s) {
+    k_em_bbox<<<em_blocks(a.n, 256) < 1024 ? em_blocks(a.n, 256) : 1024, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_grid(const EmstArgs& a, hipStream_t s) {
+    k_em_cells<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
+    const int64_t blocks = (a.ncells + kScanB * kScanI - 1) / (kScanB * kScanI);
+    k_em_scan1<<<(unsigned)blocks, kScanB, 0, s>>>(a);
+    k_em_scan2<<<1, kScanB, 0, s>>>(a, blocks);
+    k_em_scan3<<<(unsigned)blocks, kScanB, 0, s>>>(a);
+    k_em_scatter<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_core_grid(const EmstArgs& a, hipStream_t s) {
+    k_em_core_grid<<<em_blocks(a.n, kEmBlock), kEmBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_sorted_state(const EmstArgs& a, int with_core, hipStream_t s) {
+    k_em_sorted_state<<<em_blocks(a.n, 256), 256, 0, s>>>(a, with_core);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_search_grid(const EmstArgs& a, int64_t active, hipStream_t s) {
+    if (active > 0) k_em_best_grid<<<em_blocks(active, kEmBlock), kEmBlock, 0, s>>>(a, active);
     return hipGetLastError();
 }
 

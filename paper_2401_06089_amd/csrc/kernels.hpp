@@ -286,14 +286,41 @@ struct EmstArgs {
     int32_t* v;
     double* w64;               // may be null
     float* w32;
-    uint32_t* counters;        // [4] edges, components, error bits, pointer-jumping changes / active points
+    uint32_t* counters;        // [8] edges, components, error bits, pointer-jumping changes / active
+                               // points, grid leftovers
+    // uniform grid (large clouds): points sorted by cell; searches widen ring
+    // by ring and stop once no farther cell can hold a better point
+    int use_grid;
+    double gmin[kEmstMaxDim];  // grid origin
+    double h, inv_h;           // cell edge and its inverse
+    double gslack;             // distance by which rounding may misplace a point across a cell boundary
+    int32_t* fallback;         // [n] points the grid search left to a full sweep
+    int32_t gdim[kEmstMaxDim]; // cells per dimension (1 for unused dimensions)
+    int64_t gstride[kEmstMaxDim];
+    int64_t ncells;
+    uint32_t* bbox;            // [2 * kEmstMaxDim] order-preserving bits of each min and of each max, complemented
+    int32_t* cellof;           // [n] cell of each point
+    int32_t* cstart;           // [ncells + 1] first sorted position of each cell
+    int32_t* cfill;            // [ncells] points per cell, then a fill counter
+    int32_t* sorted;           // [n] point at each sorted position
+    double* spts;              // [n * kEmstMaxDim] coordinates in sorted order
+    double* score2;            // [n] core distances in sorted order
+    int32_t* scomp;            // [n] components in sorted order (refreshed every round)
+    uint8_t* partial;          // [n] the point's search stopped early: search again next round
+    uint64_t* scan_agg;        // cell-count scan: per-block sums
 };
-hipError_t launch_em_core(const EmstArgs& a, hipStream_t s);
+hipError_t launch_em_core(const EmstArgs& a, const int32_t* list, int64_t count, hipStream_t s);
 hipError_t launch_em_active(const EmstArgs& a, hipStream_t s);   // counts into counters[3]
-hipError_t launch_em_round(const EmstArgs& a, int64_t active, hipStream_t s);
+hipError_t launch_em_search(const EmstArgs& a, const int32_t* list, int64_t count, hipStream_t s);
+hipError_t launch_em_merge_edges(const EmstArgs& a, hipStream_t s);
 hipError_t launch_em_jump(const EmstArgs& a, int src, hipStream_t s);
 hipError_t launch_em_relabel(const EmstArgs& a, int src, hipStream_t s);
 hipError_t launch_em_sort_out(const EmstArgs& a, int64_t len, hipStream_t s);
+hipError_t launch_em_bbox(const EmstArgs& a, hipStream_t s);
+hipError_t launch_em_grid(const EmstArgs& a, hipStream_t s);         // cells, counts, scan, scatter
+hipError_t launch_em_core_grid(const EmstArgs& a, hipStream_t s);      // leftovers listed in fallback
+hipError_t launch_em_sorted_state(const EmstArgs& a, int with_core, hipStream_t s);
+hipError_t launch_em_search_grid(const EmstArgs& a, int64_t active, hipStream_t s);
 
 // ---- misc -----------------------------------------------------------------------
 // Clears the control block; voff1, if given, receives the offsets {0, n} of a

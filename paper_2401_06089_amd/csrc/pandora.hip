@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
@@ -1010,15 +1011,21 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
 // ---- mutual-reachability MST of a point cloud -------------------------------------
 
 struct EmstLayout {
-    size_t core2, comp, comp2, best_w, best_j, active, cmin_w, cmin_e, par0, par1, ew, ea, eb, counters;
-    int64_t len = 0;   // padded edge-list length (a power of two >= n - 1)
+    size_t core2, comp, comp2, best_w, best_j, active, cmin_w, cmin_e, par0, par1, ew, ea, eb, counters, bbox,
+        cellof, cstart, cfill, sorted, spts, score2, scomp, partial, fallback, scan_agg;
+    int64_t len = 0;        // padded edge-list length (a power of two >= n - 1)
+    int64_t max_cells = 0;  // grid cells allowed
     size_t total = 0;
 };
+
+constexpr int64_t kEmstGridMin = 2048;   // clouds at least this large use the grid
 
 EmstLayout make_emst_layout(int64_t n) {
     EmstLayout E;
     E.len = 1;
     while (E.len < n - 1) E.len <<= 1;
+    E.max_cells = n >= kEmstGridMin ? 4 * n + 16 : 0;
+    const bool grid = E.max_cells > 0;
     size_t c = 0;
     E.core2 = take(c, 8 * n);
     E.comp = take(c, 4 * n);
@@ -1033,9 +1040,76 @@ EmstLayout make_emst_layout(int64_t n) {
     E.ew = take(c, 8 * E.len);
     E.ea = take(c, 4 * E.len);
     E.eb = take(c, 4 * E.len);
-    E.counters = take(c, 16);
+    E.counters = take(c, 32);
+    E.bbox = take(c, 8 * kEmstMaxDim);
+    E.cellof = take(c, grid ? 4 * n : 0);
+    E.cstart = take(c, grid ? 4 * (E.max_cells + 1) : 0);
+    E.cfill = take(c, grid ? 4 * E.max_cells : 0);
+    E.sorted = take(c, grid ? 4 * n : 0);
+    E.spts = take(c, grid ? 8 * kEmstMaxDim * n : 0);
+    E.score2 = take(c, grid ? 8 * n : 0);
+    E.scomp = take(c, grid ? 4 * n : 0);
+    E.partial = take(c, grid ? n : 0);
+    E.fallback = take(c, grid ? 4 * n : 0);
+    E.scan_agg = take(c, grid ? 8 * ((E.max_cells + 4095) / 4096 + 1) : 0);
     E.total = c;
     return E;
+}
+
+float from_order_bits(uint32_t b) {
+    const uint32_t f = (b & 0x80000000u) ? (b & 0x7fffffffu) : ~b;
+    float x;
+    std::memcpy(&x, &f, 4);
+    return x;
+}
+
+// Grid over the bounding box: about two points per cell, at most max_cells.
+// False when every point coincides (no extent to divide).
+bool plan_grid(EmstArgs& a, const uint32_t* bbox, int64_t max_cells) {
+    double lo[kEmstMaxDim], ext[kEmstMaxDim], mag = 0.0, vol = 1.0;
+    int live = 0;
+    for (int k = 0; k < a.dim; ++k) {
+        lo[k] = (double)from_order_bits(bbox[2 * k]);
+        const double hi = (double)from_order_bits(~bbox[2 * k + 1]);
+        ext[k] = hi - lo[k];
+        mag = std::max(mag, std::max(std::fabs(lo[k]), std::fabs(hi)));
+        if (ext[k] > 0.0) {
+            vol *= ext[k];
+            ++live;
+        }
+    }
+    if (live == 0) return false;
+    double h = std::pow(vol / std::max(1.0, (double)a.n / 2.0), 1.0 / live);
+    for (int attempt = 0; attempt < 64; ++attempt) {
+        int64_t cells = 1;
+        bool fits = true;
+        for (int k = 0; k < a.dim; ++k) {
+            const double g = ext[k] > 0.0 ? std::floor(ext[k] / h) + 1.0 : 1.0;
+            if (g > (double)max_cells) fits = false;
+            a.gdim[k] = fits ? (int32_t)g : 1;
+            cells = fits ? cells * a.gdim[k] : cells;
+            if (cells > max_cells) fits = false;
+        }
+        if (fits) {
+            a.ncells = cells;
+            break;
+        }
+        h *= 1.25;
+        if (attempt == 63) return false;
+    }
+    int64_t stride = 1;
+    for (int k = 0; k < kEmstMaxDim; ++k) {
+        a.gmin[k] = k < a.dim ? lo[k] : 0.0;
+        if (k >= a.dim) a.gdim[k] = 1;
+        a.gstride[k] = stride;
+        stride *= a.gdim[k];
+    }
+    a.h = h;
+    a.inv_h = 1.0 / h;
+    // a rounded floor misplaces a point across a boundary only within a few
+    // rounding units of the coordinates' magnitude
+    a.gslack = 16.0 * (mag + h) * std::ldexp(1.0, -52);
+    return true;
 }
 
 // Synchronous: Borůvka rounds until one component, then the sorted tree.
@@ -1073,37 +1147,88 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
     a.w64 = w64;
     a.w32 = w32;
     a.counters = at<uint32_t>(d, E.counters);
+    a.bbox = at<uint32_t>(d, E.bbox);
     uint32_t* hc = static_cast<uint32_t*>(ws.host);       // pinned readback of the counters
+    auto read_counters = [&]() -> int {
+        PD_TRY(hipMemcpyAsync(hc, a.counters, 32, hipMemcpyDeviceToHost, s));
+        PD_TRY(hipStreamSynchronize(s));
+        return PANDORA_OK;
+    };
+    PD_TRY(launch_clear_words(a.counters, 8, s));
+
     // The searches are dense fp64 work: their "bytes" in the profiler are
-    // fp64 operations, 3 per coordinate and 2 more per point pair.
+    // fp64 operations, 3 per coordinate and 2 more per point pair examined
+    // (for the grid, the pairs of a full sweep).
     const double pair_ops = (double)n * (double)n * (3.0 * dim + 2.0);
-    PD_TRY(launch_clear_words(a.counters, 4, s));
-    PD_TIMED(PK_EM_CORE, pair_ops, launch_em_core(a, s));
+    if (E.max_cells > 0) {
+        PD_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(a.bbox), 2 * kEmstMaxDim, -1, s));
+        PD_TRY(launch_em_bbox(a, s));
+        PD_TRY(hipMemcpyAsync(hc, a.bbox, 8 * kEmstMaxDim, hipMemcpyDeviceToHost, s));
+        PD_TRY(hipStreamSynchronize(s));
+        uint32_t bb[2 * kEmstMaxDim];
+        std::memcpy(bb, hc, sizeof(bb));
+        a.use_grid = plan_grid(a, bb, E.max_cells) ? 1 : 0;
+    }
+    if (a.use_grid) {
+        a.cellof = at<int32_t>(d, E.cellof);
+        a.cstart = at<int32_t>(d, E.cstart);
+        a.cfill = at<int32_t>(d, E.cfill);
+        a.sorted = at<int32_t>(d, E.sorted);
+        a.spts = at<double>(d, E.spts);
+        a.score2 = at<double>(d, E.score2);
+        a.scomp = at<int32_t>(d, E.scomp);
+        a.partial = at<uint8_t>(d, E.partial);
+        a.fallback = at<int32_t>(d, E.fallback);
+        a.scan_agg = at<uint64_t>(d, E.scan_agg);
+        PD_TRY(launch_clear_words(reinterpret_cast<uint32_t*>(a.cfill), a.ncells, s));
+        PD_TRY(launch_em_grid(a, s));
+        PD_TIMED(PK_EM_CORE, pair_ops, launch_em_core_grid(a, s));
+        int rc2 = read_counters();
+        if (rc2 != PANDORA_OK) return rc2;
+        if (hc[2]) return (hc[2] & 1u) ? PANDORA_ERR_INVALID_ARG : PANDORA_ERR_HIP;
+        PD_TIMED(PK_EM_CORE, 0.0, launch_em_core(a, a.fallback, hc[4], s));
+        PD_TRY(launch_em_sorted_state(a, 1, s));
+    } else {
+        PD_TIMED(PK_EM_CORE, pair_ops, launch_em_core(a, nullptr, 0, s));
+    }
     int64_t comps = n;
     for (int round = 0; comps > 1; ++round) {
         if (round > 64) return PANDORA_ERR_HIP;           // every round at least halves the components
-        PD_TRY(launch_clear_words(a.counters + 3, 1, s));
+        PD_TRY(launch_clear_words(a.counters + 3, 2, s));
         PD_TRY(launch_em_active(a, s));
-        PD_TRY(hipMemcpyAsync(hc, a.counters, 16, hipMemcpyDeviceToHost, s));
-        PD_TRY(hipStreamSynchronize(s));
+        int rc2 = read_counters();
+        if (rc2 != PANDORA_OK) return rc2;
+        if (hc[2]) return (hc[2] & 1u) ? PANDORA_ERR_INVALID_ARG : PANDORA_ERR_HIP;
         const int64_t active = hc[3];
         if (active > n) return PANDORA_ERR_HIP;
-        PD_TIMED(PK_EM_SEARCH, (double)active * (double)n * (3.0 * dim + 2.0), launch_em_round(a, active, s));
+        if (a.use_grid) {
+            PD_TRY(launch_em_sorted_state(a, 0, s));
+            PD_TIMED(PK_EM_SEARCH, pair_ops, launch_em_search_grid(a, active, s));
+            rc2 = read_counters();
+            if (rc2 != PANDORA_OK) return rc2;
+            const int64_t left = hc[4];
+            if (left > active) return PANDORA_ERR_HIP;
+            PD_TIMED(PK_EM_SEARCH, 0.0, launch_em_search(a, a.fallback, left, s));
+        } else {
+            PD_TIMED(PK_EM_SEARCH, (double)active * (double)n * (3.0 * dim + 2.0),
+                     launch_em_search(a, a.active, active, s));
+        }
+        PD_TIMED(PK_EM_MERGE, 16.0 * (double)n, launch_em_merge_edges(a, s));
         int src = 0;
         for (int jr = 0;; ++jr) {
             if (jr > 64) return PANDORA_ERR_HIP;
             PD_TRY(launch_clear_words(a.counters + 3, 1, s));
             PD_TIMED(PK_EM_MERGE, 12.0 * (double)comps, launch_em_jump(a, src, s));
             src ^= 1;
-            PD_TRY(hipMemcpyAsync(hc, a.counters, 16, hipMemcpyDeviceToHost, s));
-            PD_TRY(hipStreamSynchronize(s));
-            if (hc[2]) return (hc[2] & 1u) ? PANDORA_ERR_INVALID_ARG : PANDORA_ERR_HIP;
+            rc2 = read_counters();
+            if (rc2 != PANDORA_OK) return rc2;
+            if (hc[2]) return PANDORA_ERR_HIP;
             if (hc[3] == 0) break;
         }
         PD_TRY(launch_clear_words(a.counters + 1, 1, s));
         PD_TIMED(PK_EM_MERGE, 40.0 * (double)n, launch_em_relabel(a, src, s));
-        PD_TRY(hipMemcpyAsync(hc, a.counters, 16, hipMemcpyDeviceToHost, s));
-        PD_TRY(hipStreamSynchronize(s));
+        rc2 = read_counters();
+        if (rc2 != PANDORA_OK) return rc2;
         if (hc[2]) return PANDORA_ERR_HIP;
         if ((int64_t)hc[1] >= comps) return PANDORA_ERR_HIP;   // no progress: cannot happen
         comps = hc[1];

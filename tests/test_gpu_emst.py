@@ -48,6 +48,19 @@ def test_matches_oracle(dim, min_pts):
     check(cloud(1500, dim, 10 * dim + min_pts, "blobs"), min_pts)
 
 
+@pytest.mark.parametrize("dim", [1, 2, 3, 4])
+@pytest.mark.parametrize("min_pts", [1, 3, 16])
+def test_grid_search_matches_oracle(dim, min_pts):
+    """Clouds of at least 2,048 points take the uniform-grid search (rings,
+    early stops, full sweeps for far points)."""
+    check(cloud(2600, dim, 100 * dim + min_pts, "blobs"), min_pts)
+
+
+@pytest.mark.parametrize("kind,n", [("uniform", 8_000), ("blobs", 8_000), ("normal", 6_000)])
+def test_grid_search_larger_clouds(kind, n):
+    check(cloud(n, 3, n, kind), 4)
+
+
 @pytest.mark.parametrize("kind", ["normal", "uniform", "grid"])
 def test_shapes_and_ties(kind):
     for n, mp in ((2, 1), (2, 2), (3, 3), (257, 4), (3000, 8)):
@@ -66,6 +79,10 @@ def test_single_point_and_errors():
     with pytest.raises(pd.PandoraError):
         pd.emst(torch.zeros((10, 5), dtype=torch.float32, device="cuda"), 2)
     check(cloud(500, 2, 2, "normal"), 3)      # the stream's workspace is fine afterwards
+    same = np.zeros((3000, 3), np.float32)    # every point equal: no extent for a grid
+    u, v, w64, w32 = pd.emst(torch.from_numpy(same).cuda(), 2)
+    assert (w64.cpu().numpy() == 0).all() and u.numel() == 2999
+    check(np.concatenate([same[:2500], cloud(600, 3, 9, "normal")]), 3)   # duplicates plus a cloud
 
 
 @pytest.mark.parametrize("seed,min_pts,mcs", [(1, 2, 10), (2, 4, 20), (3, 8, 40)])
