@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FLAT_MCS = 100   # minimum cluster size of the flat-cluster workloads
-HDB_POINTS, HDB_DIM, HDB_MIN_PTS = 200_000, 3, 2
+HDB_DIM, HDB_MIN_PTS = 3, 2
 
 WORKLOADS = {
     "c2": "two single trees, n=10,000,000 each: (a) random recursive tree, fp32 uniform [0,1) "
@@ -43,8 +43,8 @@ WORKLOADS = {
     "c3": "preferential-attachment tree, n=50,000,000, lognormal(0,1.5) fp32 weights, 5% x10 bridges",
     "c3flat": "HDBSCAN* flat clusters (min cluster size 100) of the preferential-attachment tree, "
               "n=50,000,000, lognormal(0,1.5) fp32 weights, 5% x10 bridges: dendrogram + clusters per call",
-    "hdb3d": "HDBSCAN* end to end on 200,000 uniform points in the unit cube (3D), min_pts 2, min cluster "
-             "size 100: mutual-reachability MST (brute force), dendrogram and flat clusters per call",
+    "hdb3d": "HDBSCAN* end to end on uniform points in the unit cube (3D; 10,000,000 by default), min_pts 2, "
+             "min cluster size 100: mutual-reachability MST (uniform grid), dendrogram and flat clusters per call",
     "c4": "4,096 trees, lognormal sizes in [100, 1,000,000] (~50M edges), half random-recursive "
           "half caterpillar, fp32 uniform weights, one batched call",
     "c5": "serving: Poisson arrivals at 2,000 req/s of random recursive trees with log-uniform "
@@ -163,6 +163,7 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="c5: admission budget")
     ap.add_argument("--max-batch-edges", type=int, default=8_000_000, help="c5: edge cap of one batch")
     ap.add_argument("--policy", default="small_first", choices=["fifo", "small_first"], help="c5: batching order")
+    ap.add_argument("--points", type=int, default=10_000_000, help="hdb3d: points in the cloud")
     ap.add_argument("--sample-every", type=int, default=4,
                     help="bracket the dominant kernel with HIP events on every k-th timed step")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -460,7 +461,8 @@ def run_points(args, dev):
 
     import paper_2401_06089_amd as pd
 
-    pts = torch.from_numpy(uniform_points(HDB_POINTS, HDB_DIM, 0)).to(dev)
+    npts = args.points
+    pts = torch.from_numpy(uniform_points(npts, HDB_DIM, 0)).to(dev)
     torch.cuda.synchronize()
     ks = []
 
@@ -489,11 +491,11 @@ def run_points(args, dev):
     achieved = search["bytes"] / (search["ms"] / 1000.0) / 1e12 if search["ms"] > 0 else 0.0
     out = {
         "metric": "HDBSCAN* points/sec (mutual-reachability MST + dendrogram + flat clusters)",
-        "value": HDB_POINTS * args.steps / elapsed,
+        "value": npts * args.steps / elapsed,
         "unit": "points/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "hdb3d", "description": WORKLOADS["hdb3d"], "points": HDB_POINTS, "dim": HDB_DIM,
+        "config": {"workload": "hdb3d", "description": WORKLOADS["hdb3d"], "points": npts, "dim": HDB_DIM,
                    "min_pts": HDB_MIN_PTS, "min_cluster_size": FLAT_MCS, "clusters": ks[-1] if ks else None,
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": 1000 * statistics.median(lat), "p99": 1000 * float(np.percentile(lat, 99)),

@@ -620,18 +620,33 @@ __global__ void k_fc_top_round(FlatArgs a, int src) {
 
 // Cluster of every vertex (its parent edge's cluster), its chosen cluster,
 // and the first vertex of each chosen cluster.
+// Few large clusters would make every vertex hit the same few minv words:
+// within a wave (consecutive vertices) only the first lane of each label
+// competes, since it holds that label's smallest vertex there.
 __global__ void k_fc_label(FlatArgs a, int src) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int32_t* tp = a.tp[src];
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.n; x += stride) {
-        const int32_t p = a.vp[x];
+    const int lane = lane_id();
+    for (int64_t x0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); x0 < a.n; x0 += stride) {
+        const int64_t x = x0 + lane;
         int32_t lab = -1;
-        if (p >= 0 && p < a.m) {
-            const int32_t c = a.T[p];
-            if (c >= 0 && c < a.m) lab = tp[a.cidx[c]];      // c is a born cluster or the root (m)
+        if (x < a.n) {
+            const int32_t p = a.vp[x];
+            if (p >= 0 && p < a.m) {
+                const int32_t c = a.T[p];
+                if (c >= 0 && c < a.m) lab = tp[a.cidx[c]];  // c is a born cluster or the root (m)
+            }
+            a.labels[x] = lab;
         }
-        a.labels[x] = lab;
-        if (lab >= 0 && lab < a.K) atomicMin(&a.minv[lab], (int32_t)x);
+        const bool mine = lab >= 0 && lab < a.K;
+        uint64_t open = ballot(mine);
+        while (open) {
+            const int leader = __ffsll((long long)open) - 1;
+            const int32_t l = __shfl(lab, leader, kWave);
+            const uint64_t same = ballot(mine && lab == l);
+            if (lane == leader) atomicMin(&a.minv[l], (int32_t)x);
+            open &= ~same;
+        }
     }
 }
 
