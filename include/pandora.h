@@ -187,9 +187,10 @@ PANDORA_API int pandora_flat_clusters(int64_t n, const int32_t* u, const int32_t
  * order, u[k] < v[k], with weights w64 = sqrt(squared mutual reachability)
  * (correctly rounded; may be NULL) and w32 = its fp32 rounding, ready for
  * pandora_dendrogram / pandora_flat_clusters (edge k = k-th in the order).
- * Brute force: O(n^2) distance evaluations per Boruvka round, at most
- * about log2 n rounds; n <= 2^24.  Synchronous.  Errors: INVALID_ARG (also
- * for a non-finite coordinate), OUT_OF_MEMORY, HIP.
+ * Boruvka rounds (at most about log2 n); from 2,048 points on, the searches
+ * run on a uniform grid (exact: the grid changes speed only), below that as
+ * full sweeps.  n <= 2^24.  Synchronous.  Errors: INVALID_ARG (also for a
+ * non-finite coordinate), OUT_OF_MEMORY, HIP.
  */
 PANDORA_API int pandora_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32_t* u, int32_t* v,
                              double* w64, float* w32, void* hip_stream);

@@ -10,10 +10,13 @@
 // unique.  Since sqrt is monotone and correctly rounded, ordering by mrd2
 // orders the weights sqrt(mrd2).
 //
-// Borůvka rounds: every point finds its least edge to another component by a
-// brute-force sweep over LDS tiles of all points (dense fp64 vector work,
-// no matrix core shape); a point whose previous least edge still leaves its
-// component keeps it.  Components take the least edge of their points
+// Borůvka rounds: every point finds its least edge to another component.
+// Small clouds sweep all points in LDS tiles (dense fp64 vector work, no
+// matrix-core shape); clouds of 2,048+ points search a uniform grid ring by
+// ring, stop at exact distance bounds (or at an edge the point's component
+// already has that it cannot beat), and leave isolated points to a full
+// sweep.  A point whose previous least edge still leaves its component keeps
+// it.  Components take the least edge of their points
 // (two atomic minima: weight bits, then endpoints), hook along it (a
 // mutual pair keeps the smaller root), and pointer jumping relabels.  Each
 // round at least halves the components.  The tree's edges are then sorted
