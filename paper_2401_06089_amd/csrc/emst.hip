@@ -117,8 +117,11 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t*
 // only lose points.  Such points report it at once; the others are listed
 // for a new search.
 __global__ void k_em_active(EmstArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n) return;
+    // on the grid, points are listed in cell order, so that neighbouring
+    // threads search neighbouring cells (shared lines in the caches)
+    const int64_t i = a.use_grid ? a.sorted[t] : t;
     const int32_t j = a.best_j[i];
     const int32_t mc = a.comp[i];
     if (j >= 0 && a.comp[j] != mc && !(a.use_grid && a.partial[i])) {
@@ -263,6 +266,49 @@ __global__ void k_em_bitonic(EmstArgs a, int64_t len, int64_t k, int64_t j) {
         a.ea[l] = ai;
         a.eb[i] = bl;
         a.eb[l] = bi;
+    }
+}
+
+// The steps with partner distance j < kSortTile stay inside one tile of
+// consecutive elements: a workgroup does all of them for a stage k in LDS
+// (k <= 0 runs every stage up to kSortTile, i.e. sorts each tile).
+constexpr int kSortTile = 2048;
+__global__ __launch_bounds__(kSortTile / 2) void k_em_bitonic_tile(EmstArgs a, int64_t kstage) {
+    __shared__ uint64_t s_w[kSortTile];
+    __shared__ int32_t s_a[kSortTile], s_b[kSortTile];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int t = threadIdx.x; t < kSortTile; t += blockDim.x) {
+        s_w[t] = a.ew[base + t];
+        s_a[t] = a.ea[base + t];
+        s_b[t] = a.eb[base + t];
+    }
+    __syncthreads();
+    const int64_t k_lo = kstage > 0 ? kstage : 2, k_hi = kstage > 0 ? kstage : kSortTile;
+    for (int64_t k = k_lo; k <= k_hi; k <<= 1) {
+        for (int64_t j = (k >> 1) < (kSortTile >> 1) ? (k >> 1) : (kSortTile >> 1); j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < kSortTile; t += blockDim.x) {
+                const int l = t ^ (int)j;
+                if (l <= t) continue;
+                const bool up = ((base + t) & k) == 0;
+                const uint64_t wi = s_w[t], wl = s_w[l];
+                const int32_t ai = s_a[t], al = s_a[l], bi = s_b[t], bl = s_b[l];
+                const bool gt = wi > wl || (wi == wl && (ai > al || (ai == al && bi > bl)));
+                if (gt == up) {
+                    s_w[t] = wl;
+                    s_w[l] = wi;
+                    s_a[t] = al;
+                    s_a[l] = ai;
+                    s_b[t] = bl;
+                    s_b[l] = bi;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < kSortTile; t += blockDim.x) {
+        a.ew[base + t] = s_w[t];
+        a.ea[base + t] = s_a[t];
+        a.eb[base + t] = s_b[t];
     }
 }
 
@@ -505,8 +551,9 @@ __device__ __forceinline__ int max_ring(const EmstArgs& a) {
 // Core distances by widening rings: stop once the K-th smallest is no more
 // than the bound for everything farther out.
 __global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
-    if (i >= a.n) return;
+    const int64_t q = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;   // sorted position: cell order
+    if (q >= a.n) return;
+    const int64_t i = a.sorted[q];
     const int K = a.min_pts - 1;
     double me[kEmstMaxDim];
     int32_t c[kEmstMaxDim];
@@ -516,9 +563,8 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
         me[k] = 0.0;
         c[k] = 0;
         if (k < a.dim) {
-            const float f = a.pts[i * a.dim + k];
-            bad |= !isfinite(f);
-            me[k] = (double)f;
+            me[k] = a.spts[q * kEmstMaxDim + k];
+            bad |= !isfinite(me[k]);
             c[k] = cell_coord(a, me[k], k);
         }
     }
@@ -709,8 +755,20 @@ hipError_t launch_em_relabel(const EmstArgs& a, int src, hipStream_t s) {
 hipError_t launch_em_sort_out(const EmstArgs& a, int64_t len, hipStream_t s) {
     const int64_t m = a.n - 1;
     if (len > m) k_em_pad<<<em_blocks(len - m, 256), 256, 0, s>>>(a, m, len);
-    for (int64_t k = 2; k <= len; k <<= 1)
-        for (int64_t j = k >> 1; j > 0; j >>= 1) k_em_bitonic<<<em_blocks(len, 256), 256, 0, s>>>(a, len, k, j);
+    if (len < kSortTile) {
+        for (int64_t k = 2; k <= len; k <<= 1)
+            for (int64_t j = k >> 1; j > 0; j >>= 1) k_em_bitonic<<<em_blocks(len, 256), 256, 0, s>>>(a, len, k, j);
+    } else {
+        // tiles first, then per stage: the long-distance steps in global
+        // memory, the rest of the stage inside each tile
+        const unsigned tiles = (unsigned)(len / kSortTile);
+        k_em_bitonic_tile<<<tiles, kSortTile / 2, 0, s>>>(a, 0);
+        for (int64_t k = 2 * kSortTile; k <= len; k <<= 1) {
+            for (int64_t j = k >> 1; j >= kSortTile; j >>= 1)
+                k_em_bitonic<<<em_blocks(len, 256), 256, 0, s>>>(a, len, k, j);
+            k_em_bitonic_tile<<<tiles, kSortTile / 2, 0, s>>>(a, k);
+        }
+    }
     k_em_out<<<em_blocks(m, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
