@@ -49,6 +49,38 @@ __device__ __forceinline__ bool key_less(double w, int32_t lo, int32_t hi, doubl
     return w < bw || (w == bw && (lo < blo || (lo == blo && hi < bhi)));
 }
 
+// Atomic minimum of val into base[key] for the lanes with act.  Lanes that
+// share the first active lane's key (neighbouring points usually share a
+// component) send one combined minimum.  Every lane of the wave must call it.
+__device__ void wave_min_into(uint64_t* base, int32_t key, uint64_t val, bool act) {
+    const uint64_t m = ballot(act);
+    if (!m) return;
+    const int leader = __ffsll((long long)m) - 1;
+    const int32_t k0 = __shfl(key, leader, kWave);
+    const bool same = act && key == k0;
+    uint64_t v = same ? val : ~0ull;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const uint64_t o = __shfl_xor(v, d, kWave);
+        v = o < v ? o : v;
+    }
+    if (lane_id() == leader) atomicMin((unsigned long long*)&base[k0], (unsigned long long)v);
+    if (act && !same) atomicMin((unsigned long long*)&base[key], (unsigned long long)val);
+}
+
+// One atomic per wave for a list append or a count: returns each wanting
+// lane's slot (the lanes' order within the wave is kept).  Every lane of the
+// wave must call it.
+__device__ uint32_t wave_append(uint32_t* ctr, bool want) {
+    const uint64_t m = ballot(want);
+    if (!m) return 0;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(ctr, (uint32_t)popc64(m));
+    base = __shfl(base, leader, kWave);
+    return base + (uint32_t)popc64(m & lanemask_lt());
+}
+
 // Core distances: each thread keeps the K smallest d2 of its point in
 // registers (sorted, fully unrolled so that nothing spills).
 // With a list, only the listed points (the grid search's leftovers), and
@@ -118,18 +150,22 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t*
 // for a new search.
 __global__ void k_em_active(EmstArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.n) return;
-    // on the grid, points are listed in cell order, so that neighbouring
-    // threads search neighbouring cells (shared lines in the caches)
-    const int64_t i = a.use_grid ? a.sorted[t] : t;
-    const int32_t j = a.best_j[i];
-    const int32_t mc = a.comp[i];
-    if (j >= 0 && a.comp[j] != mc && !(a.use_grid && a.partial[i])) {
-        atomicMin((unsigned long long*)&a.cmin_w[mc], (unsigned long long)__double_as_longlong(a.best_w[i]));
-    } else {
-        const uint32_t k = atomicAdd(&a.counters[3], 1u);
-        a.active[k] = (int32_t)i;
+    bool keep = false;
+    int32_t mc = 0;
+    uint64_t w = 0;
+    if (t < a.n) {
+        // on the grid, points are listed in cell order, so that neighbouring
+        // threads search neighbouring cells (shared lines in the caches)
+        const int64_t i = a.use_grid ? a.sorted[t] : t;
+        const int32_t j = a.best_j[i];
+        mc = a.comp[i];
+        keep = j >= 0 && a.comp[j] != mc && !(a.use_grid && a.partial[i]);
+        if (keep) w = (uint64_t)__double_as_longlong(a.best_w[i]);
     }
+    const bool search = t < a.n && !keep;
+    const uint32_t k = wave_append(&a.counters[3], search);
+    if (search) a.active[k] = (int32_t)(a.use_grid ? a.sorted[t] : t);
+    wave_min_into(a.cmin_w, mc, w, keep);
 }
 
 // Every listed point's least edge to another component.
@@ -174,8 +210,8 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best(EmstArgs a, const int32_t*
     if (i < a.n) {
         a.best_w[i] = bw;
         a.best_j[i] = bj;
-        if (bj >= 0) atomicMin((unsigned long long*)&a.cmin_w[mc], (unsigned long long)__double_as_longlong(bw));
     }
+    wave_min_into(a.cmin_w, mc, (uint64_t)__double_as_longlong(bw), i < a.n && bj >= 0);
 }
 
 // Among the points whose edge has the component's least weight, the least endpoints.
@@ -194,25 +230,30 @@ __global__ void k_em_cmin(EmstArgs a) {
 // the smaller root stays a root and records the edge once.
 __global__ void k_em_hook(EmstArgs a) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.n || a.comp[c] != (int32_t)c) return;
-    const uint64_t e = a.cmin_e[c];
-    if (e == ~0ull) {                                     // no edge out: the last component
-        a.parent[0][c] = (int32_t)c;
-        return;
+    bool record = false;
+    int32_t lo = 0, hi = 0;
+    if (c < a.n && a.comp[c] == (int32_t)c) {
+        const uint64_t e = a.cmin_e[c];
+        if (e == ~0ull) {                                 // no edge out: the last component
+            a.parent[0][c] = (int32_t)c;
+        } else {
+            lo = (int32_t)(e >> 32);
+            hi = (int32_t)(e & 0xffffffffu);
+            if (lo < 0 || hi >= a.n || lo >= hi) {
+                atomicOr(&a.counters[2], 2u);
+                a.parent[0][c] = (int32_t)c;
+            } else {
+                const int32_t clo = a.comp[lo], chi = a.comp[hi];
+                const int32_t other = clo == (int32_t)c ? chi : clo;
+                const bool mutual = a.cmin_e[other] == e;
+                const bool stays = mutual && (int32_t)c < other;
+                a.parent[0][c] = stays ? (int32_t)c : other;
+                record = !mutual || stays;
+            }
+        }
     }
-    const int32_t lo = (int32_t)(e >> 32), hi = (int32_t)(e & 0xffffffffu);
-    if (lo < 0 || hi >= a.n || lo >= hi) {
-        atomicOr(&a.counters[2], 2u);
-        a.parent[0][c] = (int32_t)c;
-        return;
-    }
-    const int32_t clo = a.comp[lo], chi = a.comp[hi];
-    const int32_t other = clo == (int32_t)c ? chi : clo;
-    const bool mutual = a.cmin_e[other] == e;
-    const bool stays = mutual && (int32_t)c < other;
-    a.parent[0][c] = stays ? (int32_t)c : other;
-    if (!mutual || stays) {
-        const uint32_t k = atomicAdd(&a.counters[0], 1u);
+    const uint32_t k = wave_append(&a.counters[0], record);
+    if (record) {
         if (k < (uint32_t)(a.n - 1)) {
             a.ew[k] = a.cmin_w[c];
             a.ea[k] = lo;
@@ -225,22 +266,28 @@ __global__ void k_em_hook(EmstArgs a) {
 
 __global__ void k_em_jump(EmstArgs a, int src) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.n || a.comp[c] != (int32_t)c) return;
-    const int32_t p = a.parent[src][c];
-    const int32_t pp = (p >= 0 && p < a.n) ? a.parent[src][p] : p;
-    a.parent[src ^ 1][c] = pp;
-    if (pp != p) atomicOr(&a.counters[3], 1u);
+    bool changed = false;
+    if (c < a.n && a.comp[c] == (int32_t)c) {
+        const int32_t p = a.parent[src][c];
+        const int32_t pp = (p >= 0 && p < a.n) ? a.parent[src][p] : p;
+        a.parent[src ^ 1][c] = pp;
+        changed = pp != p;
+    }
+    if (ballot(changed) != 0 && lane_id() == 0) atomicOr(&a.counters[3], 1u);
 }
 
 // New component of every point; the per-component minima start over.
 __global__ void k_em_relabel(EmstArgs a, int src) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    const int32_t r = a.parent[src][a.comp[i]];
-    a.comp2[i] = r;
-    a.cmin_w[i] = ~0ull;
-    a.cmin_e[i] = ~0ull;
-    if (r == (int32_t)i) atomicAdd(&a.counters[1], 1u);
+    bool root = false;
+    if (i < a.n) {
+        const int32_t r = a.parent[src][a.comp[i]];
+        a.comp2[i] = r;
+        a.cmin_w[i] = ~0ull;
+        a.cmin_e[i] = ~0ull;
+        root = r == (int32_t)i;
+    }
+    (void)wave_append(&a.counters[1], root);
 }
 
 __global__ void k_em_copy_comp(EmstArgs a) {
@@ -628,8 +675,8 @@ __global__ void k_em_sorted_state(EmstArgs a, int with_core) {
 // it searches again next round).
 __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t count) {
     const int64_t slot = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
-    if (slot >= count) return;
-    const int32_t i = a.active[slot];
+    const bool live = slot < count;
+    const int32_t i = live ? a.active[slot] : 0;
     double me[kEmstMaxDim];
     int32_t c[kEmstMaxDim];
 #pragma unroll
@@ -641,10 +688,10 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
     const int32_t mc = a.comp[i];
     double bw = INFINITY;
     int32_t blo = INT32_MAX, bhi = INT32_MAX, bj = -1;
-    bool partial = false, done = false;
+    bool partial = false, done = !live;
     const int rmax = max_ring(a);
     const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
-    for (int r = 0; r <= rcap; ++r) {
+    for (int r = 0; live && r <= rcap; ++r) {
         for_ring(a, c, r, [&](int32_t p0, int32_t p1) {
             for (int32_t p = p0; p < p1; ++p) {
                 if (a.scomp[p] == mc) continue;
@@ -673,16 +720,18 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
             break;
         }
     }
-    if (!done) {                                          // far from other components: full sweep
+    const bool report = live && done;
+    if (live && !done) {                                  // far from other components: full sweep
         a.partial[i] = 0;
         const uint32_t k = atomicAdd(&a.counters[4], 1u);
         a.fallback[k] = i;
-        return;
     }
-    a.best_w[i] = bw;
-    a.best_j[i] = bj;
-    a.partial[i] = partial ? 1 : 0;
-    if (bj >= 0) atomicMin((unsigned long long*)&a.cmin_w[mc], (unsigned long long)__double_as_longlong(bw));
+    if (report) {
+        a.best_w[i] = bw;
+        a.best_j[i] = bj;
+        a.partial[i] = partial ? 1 : 0;
+    }
+    wave_min_into(a.cmin_w, mc, (uint64_t)__double_as_longlong(bw), report && bj >= 0);
 }
 
 inline unsigned em_blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
