@@ -502,7 +502,7 @@ def run_points(args, dev):
                        "per": "step"},
         "roofline": {"bound": "alu", "kernel": "emst_search", "achieved": achieved,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "ops": "fp64 operations of the point-pair sweeps (3 per coordinate + 2)",
+                     "traffic": None, "ops": "fp64 operations of the point pairs the searches examine (3 per coordinate + 2), counted on the device in the profiled step",
                      "launches": search["launches"]},
         "stages": {k: {"ms": v["ms"], "launches": v["launches"]} for k, v in stages.items() if v["launches"]},
     }

@@ -15,8 +15,10 @@
 // matrix-core shape); clouds of 2,048+ points search a uniform grid ring by
 // ring, stop at exact distance bounds (or at an edge the point's component
 // already has that it cannot beat), and leave isolated points to a full
-// sweep.  A point whose previous least edge still leaves its component keeps
-// it.  Components take the least edge of their points
+// sweep.  On the grid every per-point array is kept in cell order (a point's
+// slot), so that the passes over all points read and write them in order
+// and a search's neighbours sit next to it.  A point whose previous least
+// edge still leaves its component keeps it.  Components take the least edge of their points
 // (two atomic minima: weight bits, then endpoints), hook along it (a
 // mutual pair keeps the smaller root), and pointer jumping relabels.  Each
 // round at least halves the components.  The tree's edges are then sorted
@@ -49,6 +51,20 @@ __device__ __forceinline__ bool key_less(double w, int32_t lo, int32_t hi, doubl
     return w < bw || (w == bw && (lo < blo || (lo == blo && hi < bhi)));
 }
 
+// Input index of the point in slot p, and the slot of input index id (slots
+// are sorted positions on the grid, input indices otherwise).
+__device__ __forceinline__ int32_t id_of(const EmstArgs& a, int64_t p) {
+    return a.use_grid ? a.sorted[p] : (int32_t)p;
+}
+__device__ __forceinline__ int64_t slot_of(const EmstArgs& a, int32_t id) {
+    return a.use_grid ? (int64_t)a.slotof[id] : (int64_t)id;
+}
+
+// Coordinate k of the point in slot p, widened to fp64.
+__device__ __forceinline__ double coord(const EmstArgs& a, int64_t p, int k) {
+    return a.use_grid ? a.spts[p * kEmstMaxDim + k] : (double)a.pts[p * a.dim + k];
+}
+
 // Atomic minimum of val into base[key] for the lanes with act.  Lanes that
 // share the first active lane's key (neighbouring points usually share a
 // component) send one combined minimum.  Every lane of the wave must call it.
@@ -64,26 +80,57 @@ __device__ void wave_min_into(uint64_t* base, int32_t key, uint64_t val, bool ac
         const uint64_t o = __shfl_xor(v, d, kWave);
         v = o < v ? o : v;
     }
-    if (lane_id() == leader) atomicMin((unsigned long long*)&base[k0], (unsigned long long)v);
-    if (act && !same) atomicMin((unsigned long long*)&base[key], (unsigned long long)val);
+    // a load first: late in the merging many waves share a few large
+    // components, and most of their atomics would change nothing
+    if (lane_id() == leader && v < __hip_atomic_load(&base[k0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin((unsigned long long*)&base[k0], (unsigned long long)v);
+    if (act && !same && val < __hip_atomic_load(&base[key], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin((unsigned long long*)&base[key], (unsigned long long)val);
 }
 
-// One atomic per wave for a list append or a count: returns each wanting
-// lane's slot (the lanes' order within the wave is kept).  Every lane of the
-// wave must call it.
-__device__ uint32_t wave_append(uint32_t* ctr, bool want) {
-    const uint64_t m = ballot(want);
-    if (!m) return 0;
-    const int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(ctr, (uint32_t)popc64(m));
-    base = __shfl(base, leader, kWave);
-    return base + (uint32_t)popc64(m & lanemask_lt());
+// Adds every lane's count into one slot per block, one atomic per wave.
+// Every lane of the wave must call it.
+__device__ void wave_count(uint64_t* slots, uint32_t v) {
+    uint64_t t = v;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) t += __shfl_xor(t, d, kWave);
+    if (lane_id() == 0 && t != 0)
+        atomicAdd((unsigned long long*)&slots[blockIdx.x % kEmstPairSlots], (unsigned long long)t);
 }
+
+// A list append for a whole block of kThreads, with one atomic per block
+// (an atomic from every wave of a pass over all points serialises on the
+// counter): returns each wanting thread's slot, consecutive in thread order.
+// Every thread of the block must call it.
+template <int kThreads>
+__device__ uint32_t block_append(uint32_t* ctr, bool want) {
+    constexpr int kWaves = kThreads / kWave;
+    __shared__ uint32_t s_cnt[kWaves];
+    __shared__ uint32_t s_base;
+    const uint64_t m = ballot(want);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) s_cnt[w] = (uint32_t)popc64(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < kWaves; ++k) {
+            const uint32_t t = s_cnt[k];
+            s_cnt[k] = run;
+            run += t;
+        }
+        s_base = run ? atomicAdd(ctr, run) : 0u;
+    }
+    __syncthreads();
+    const uint32_t slot = s_base + s_cnt[w] + (uint32_t)popc64(m & lanemask_lt());
+    __syncthreads();
+    return slot;
+}
+
+constexpr int kEmPass = 1024;    // block of the passes over all points that append or count
 
 // Core distances: each thread keeps the K smallest d2 of its point in
 // registers (sorted, fully unrolled so that nothing spills).
-// With a list, only the listed points (the grid search's leftovers), and
+// With a list, only the listed slots (the grid search's leftovers), and
 // nothing but their core distance is written.
 __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t* list, int64_t count) {
     __shared__ double s_p[kEmBlock][kEmstMaxDim];
@@ -96,9 +143,8 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t*
     for (int k = 0; k < kEmstMaxDim; ++k) {
         me[k] = 0.0;
         if (i < a.n && k < a.dim) {
-            const float f = a.pts[i * a.dim + k];
-            bad |= !isfinite(f);
-            me[k] = (double)f;
+            me[k] = coord(a, i, k);
+            bad |= !isfinite(me[k]);
         }
     }
     double top[kEmMaxK];
@@ -110,7 +156,7 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t*
         const int64_t jl = j0 + threadIdx.x;
 #pragma unroll
         for (int k = 0; k < kEmstMaxDim; ++k)
-            s_p[threadIdx.x][k] = (jl < a.n && k < a.dim) ? (double)a.pts[jl * a.dim + k] : 0.0;
+            s_p[threadIdx.x][k] = (jl < a.n && k < a.dim) ? coord(a, jl, k) : 0.0;
         __syncthreads();
         if (i >= a.n || K == 0) continue;
         const int cnt = a.n - j0 < kEmBlock ? (int)(a.n - j0) : kEmBlock;
@@ -147,24 +193,22 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t*
 // A point's least edge to another component stays its least edge while its
 // other end is still outside the point's (grown) component: the candidates
 // only lose points.  Such points report it at once; the others are listed
-// for a new search.
-__global__ void k_em_active(EmstArgs a) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// for a new search (in slot order: on the grid, neighbouring threads then
+// search neighbouring cells and share lines in the caches).
+__global__ __launch_bounds__(kEmPass) void k_em_active(EmstArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool keep = false;
     int32_t mc = 0;
     uint64_t w = 0;
-    if (t < a.n) {
-        // on the grid, points are listed in cell order, so that neighbouring
-        // threads search neighbouring cells (shared lines in the caches)
-        const int64_t i = a.use_grid ? a.sorted[t] : t;
+    if (i < a.n) {
         const int32_t j = a.best_j[i];
         mc = a.comp[i];
         keep = j >= 0 && a.comp[j] != mc && !(a.use_grid && a.partial[i]);
         if (keep) w = (uint64_t)__double_as_longlong(a.best_w[i]);
     }
-    const bool search = t < a.n && !keep;
-    const uint32_t k = wave_append(&a.counters[3], search);
-    if (search) a.active[k] = (int32_t)(a.use_grid ? a.sorted[t] : t);
+    const bool search = i < a.n && !keep;
+    const uint32_t k = block_append<kEmPass>(&a.counters[3], search);
+    if (search) a.active[k] = (int32_t)i;
     wave_min_into(a.cmin_w, mc, w, keep);
 }
 
@@ -173,13 +217,15 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best(EmstArgs a, const int32_t*
     __shared__ double s_p[kEmBlock][kEmstMaxDim];
     __shared__ double s_c[kEmBlock];
     __shared__ int32_t s_comp[kEmBlock];
+    __shared__ int32_t s_id[kEmBlock];
     const int64_t slot = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
     const int64_t i = slot < count ? list[slot] : a.n;
     double me[kEmstMaxDim];
 #pragma unroll
-    for (int k = 0; k < kEmstMaxDim; ++k) me[k] = (i < a.n && k < a.dim) ? (double)a.pts[i * a.dim + k] : 0.0;
+    for (int k = 0; k < kEmstMaxDim; ++k) me[k] = (i < a.n && k < a.dim) ? coord(a, i, k) : 0.0;
     const double ci = i < a.n ? a.core2[i] : 0.0;
     const int32_t mc = i < a.n ? a.comp[i] : -1;
+    const int32_t io = i < a.n ? id_of(a, i) : 0;
     double bw = INFINITY;
     int32_t blo = INT32_MAX, bhi = INT32_MAX, bj = -1;
     for (int64_t j0 = 0; j0 < a.n; j0 += kEmBlock) {
@@ -187,9 +233,10 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best(EmstArgs a, const int32_t*
         const int64_t jl = j0 + threadIdx.x;
 #pragma unroll
         for (int k = 0; k < kEmstMaxDim; ++k)
-            s_p[threadIdx.x][k] = (jl < a.n && k < a.dim) ? (double)a.pts[jl * a.dim + k] : 0.0;
+            s_p[threadIdx.x][k] = (jl < a.n && k < a.dim) ? coord(a, jl, k) : 0.0;
         s_c[threadIdx.x] = jl < a.n ? a.core2[jl] : 0.0;
         s_comp[threadIdx.x] = jl < a.n ? a.comp[jl] : mc;
+        s_id[threadIdx.x] = jl < a.n ? id_of(a, jl) : 0;
         __syncthreads();
         if (i >= a.n) continue;
         const int cnt = a.n - j0 < kEmBlock ? (int)(a.n - j0) : kEmBlock;
@@ -197,13 +244,13 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best(EmstArgs a, const int32_t*
             if (s_comp[jj] == mc) continue;
             const double d = d2_of(me, s_p[jj], a.dim);
             const double w = fmax(fmax(ci, s_c[jj]), d);
-            const int32_t j = (int32_t)(j0 + jj);
-            const int32_t lo = j < (int32_t)i ? j : (int32_t)i, hi = j < (int32_t)i ? (int32_t)i : j;
+            const int32_t j = s_id[jj];
+            const int32_t lo = j < io ? j : io, hi = j < io ? io : j;
             if (key_less(w, lo, hi, bw, blo, bhi)) {
                 bw = w;
                 blo = lo;
                 bhi = hi;
-                bj = j;
+                bj = (int32_t)(j0 + jj);
             }
         }
     }
@@ -222,13 +269,14 @@ __global__ void k_em_cmin(EmstArgs a) {
     if (j < 0) return;
     const int32_t c = a.comp[i];
     if ((uint64_t)__double_as_longlong(a.best_w[i]) != a.cmin_w[c]) return;
-    const uint64_t lo = (uint64_t)(uint32_t)(j < i ? j : (int32_t)i), hi = (uint64_t)(uint32_t)(j < i ? (int32_t)i : j);
+    const int32_t io = id_of(a, i), jo = id_of(a, j);
+    const uint64_t lo = (uint64_t)(uint32_t)(jo < io ? jo : io), hi = (uint64_t)(uint32_t)(jo < io ? io : jo);
     atomicMin((unsigned long long*)&a.cmin_e[c], (unsigned long long)((lo << 32) | hi));
 }
 
 // Each component hooks to the one across its least edge; of a mutual pair
 // the smaller root stays a root and records the edge once.
-__global__ void k_em_hook(EmstArgs a) {
+__global__ __launch_bounds__(kEmPass) void k_em_hook(EmstArgs a) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool record = false;
     int32_t lo = 0, hi = 0;
@@ -243,7 +291,7 @@ __global__ void k_em_hook(EmstArgs a) {
                 atomicOr(&a.counters[2], 2u);
                 a.parent[0][c] = (int32_t)c;
             } else {
-                const int32_t clo = a.comp[lo], chi = a.comp[hi];
+                const int32_t clo = a.comp[slot_of(a, lo)], chi = a.comp[slot_of(a, hi)];
                 const int32_t other = clo == (int32_t)c ? chi : clo;
                 const bool mutual = a.cmin_e[other] == e;
                 const bool stays = mutual && (int32_t)c < other;
@@ -252,7 +300,7 @@ __global__ void k_em_hook(EmstArgs a) {
             }
         }
     }
-    const uint32_t k = wave_append(&a.counters[0], record);
+    const uint32_t k = block_append<kEmPass>(&a.counters[0], record);
     if (record) {
         if (k < (uint32_t)(a.n - 1)) {
             a.ew[k] = a.cmin_w[c];
@@ -273,11 +321,13 @@ __global__ void k_em_jump(EmstArgs a, int src) {
         a.parent[src ^ 1][c] = pp;
         changed = pp != p;
     }
-    if (ballot(changed) != 0 && lane_id() == 0) atomicOr(&a.counters[3], 1u);
+    if (__syncthreads_or(changed) && threadIdx.x == 0 &&
+        __hip_atomic_load(&a.counters[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        atomicOr(&a.counters[3], 1u);
 }
 
 // New component of every point; the per-component minima start over.
-__global__ void k_em_relabel(EmstArgs a, int src) {
+__global__ __launch_bounds__(kEmPass) void k_em_relabel(EmstArgs a, int src) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool root = false;
     if (i < a.n) {
@@ -287,7 +337,8 @@ __global__ void k_em_relabel(EmstArgs a, int src) {
         a.cmin_e[i] = ~0ull;
         root = r == (int32_t)i;
     }
-    (void)wave_append(&a.counters[1], root);
+    const int roots = __syncthreads_count(root);
+    if (threadIdx.x == 0 && roots) atomicAdd(&a.counters[1], (uint32_t)roots);
 }
 
 __global__ void k_em_copy_comp(EmstArgs a) {
@@ -552,6 +603,7 @@ __global__ void k_em_scatter(EmstArgs a) {
     const int32_t cell = a.cellof[i];
     const int64_t pos = (int64_t)a.cstart[cell] + atomicAdd(&a.cfill[cell], 1);
     a.sorted[pos] = (int32_t)i;
+    a.slotof[i] = (int32_t)pos;
 #pragma unroll
     for (int k = 0; k < kEmstMaxDim; ++k) a.spts[pos * kEmstMaxDim + k] = k < a.dim ? (double)a.pts[i * a.dim + k] : 0.0;
 }
@@ -597,10 +649,8 @@ __device__ __forceinline__ int max_ring(const EmstArgs& a) {
 
 // Core distances by widening rings: stop once the K-th smallest is no more
 // than the bound for everything farther out.
-__global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
-    const int64_t q = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;   // sorted position: cell order
-    if (q >= a.n) return;
-    const int64_t i = a.sorted[q];
+// Returns the pairs examined.
+__device__ __forceinline__ uint32_t core_grid_point(const EmstArgs& a, int64_t i) {
     const int K = a.min_pts - 1;
     double me[kEmstMaxDim];
     int32_t c[kEmstMaxDim];
@@ -610,7 +660,7 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
         me[k] = 0.0;
         c[k] = 0;
         if (k < a.dim) {
-            me[k] = a.spts[q * kEmstMaxDim + k];
+            me[k] = a.spts[i * kEmstMaxDim + k];
             bad |= !isfinite(me[k]);
             c[k] = cell_coord(a, me[k], k);
         }
@@ -620,6 +670,7 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
 #pragma unroll
     for (int t = 0; t < kEmMaxK; ++t) top[t] = INFINITY;
     double thr = INFINITY;
+    uint32_t pairs = 0;
     bool done = K == 0;
     if (K > 0) {
         const int rmax = max_ring(a);
@@ -627,8 +678,9 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
         for (int r = 0; r <= rcap; ++r) {
             for_ring(a, c, r, [&](int32_t p0, int32_t p1) {
                 for (int32_t p = p0; p < p1; ++p) {
-                    if (a.sorted[p] == (int32_t)i) continue;
+                    if (p == i) continue;
                     const double d = d2_of(me, a.spts + (int64_t)p * kEmstMaxDim, a.dim);
+                    ++pairs;
                     if (d >= thr) continue;
 #pragma unroll
                     for (int t = kEmMaxK - 1; t >= 1; --t) top[t] = fmin(top[t], fmax(top[t - 1], d));
@@ -658,14 +710,13 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
     a.partial[i] = 0;
     a.cmin_w[i] = ~0ull;
     a.cmin_e[i] = ~0ull;
+    return pairs;
 }
 
-__global__ void k_em_sorted_state(EmstArgs a, int with_core) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    const int32_t j = a.sorted[p];
-    a.scomp[p] = a.comp[j];
-    if (with_core) a.score2[p] = a.core2[j];
+__global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
+    const int64_t q = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;   // sorted position: cell order
+    const uint32_t pairs = q < a.n ? core_grid_point(a, q) : 0u;
+    if (a.count_pairs) wave_count(a.pairs, pairs);
 }
 
 // Least edge to another component by widening rings.  The search ends when
@@ -677,11 +728,12 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
     const int64_t slot = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
     const bool live = slot < count;
     const int32_t i = live ? a.active[slot] : 0;
+    const int32_t io = a.sorted[i];
     double me[kEmstMaxDim];
     int32_t c[kEmstMaxDim];
 #pragma unroll
     for (int k = 0; k < kEmstMaxDim; ++k) {
-        me[k] = k < a.dim ? (double)a.pts[(int64_t)i * a.dim + k] : 0.0;
+        me[k] = k < a.dim ? a.spts[(int64_t)i * kEmstMaxDim + k] : 0.0;
         c[k] = k < a.dim ? cell_coord(a, me[k], k) : 0;
     }
     const double ci = a.core2[i];
@@ -689,22 +741,24 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
     double bw = INFINITY;
     int32_t blo = INT32_MAX, bhi = INT32_MAX, bj = -1;
     bool partial = false, done = !live;
+    uint32_t pairs = 0;
     const int rmax = max_ring(a);
     const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
     for (int r = 0; live && r <= rcap; ++r) {
         for_ring(a, c, r, [&](int32_t p0, int32_t p1) {
             for (int32_t p = p0; p < p1; ++p) {
-                if (a.scomp[p] == mc) continue;
+                if (a.comp[p] == mc) continue;
                 const double d = d2_of(me, a.spts + (int64_t)p * kEmstMaxDim, a.dim);
-                const double w = fmax(fmax(ci, a.score2[p]), d);
+                ++pairs;
+                const double w = fmax(fmax(ci, a.core2[p]), d);
                 if (w > bw) continue;
                 const int32_t j = a.sorted[p];
-                const int32_t lo = j < i ? j : i, hi = j < i ? i : j;
+                const int32_t lo = j < io ? j : io, hi = j < io ? io : j;
                 if (key_less(w, lo, hi, bw, blo, bhi)) {
                     bw = w;
                     blo = lo;
                     bhi = hi;
-                    bj = j;
+                    bj = p;
                 }
             }
         });
@@ -732,6 +786,7 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
         a.partial[i] = partial ? 1 : 0;
     }
     wave_min_into(a.cmin_w, mc, (uint64_t)__double_as_longlong(bw), report && bj >= 0);
+    if (a.count_pairs) wave_count(a.pairs, pairs);
 }
 
 inline unsigned em_blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -745,7 +800,7 @@ hipError_t launch_em_core(const EmstArgs& a, const int32_t* list, int64_t count,
 }
 
 hipError_t launch_em_active(const EmstArgs& a, hipStream_t s) {
-    k_em_active<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
+    k_em_active<<<em_blocks(a.n, kEmPass), kEmPass, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -756,7 +811,7 @@ hipError_t launch_em_search(const EmstArgs& a, const int32_t* list, int64_t coun
 
 hipError_t launch_em_merge_edges(const EmstArgs& a, hipStream_t s) {
     k_em_cmin<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
-    k_em_hook<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
+    k_em_hook<<<em_blocks(a.n, kEmPass), kEmPass, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -780,11 +835,6 @@ hipError_t launch_em_core_grid(const EmstArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_em_sorted_state(const EmstArgs& a, int with_core, hipStream_t s) {
-    k_em_sorted_state<<<em_blocks(a.n, 256), 256, 0, s>>>(a, with_core);
-    return hipGetLastError();
-}
-
 hipError_t launch_em_search_grid(const EmstArgs& a, int64_t active, hipStream_t s) {
     if (active > 0) k_em_best_grid<<<em_blocks(active, kEmBlock), kEmBlock, 0, s>>>(a, active);
     return hipGetLastError();
@@ -796,7 +846,7 @@ hipError_t launch_em_jump(const EmstArgs& a, int src, hipStream_t s) {
 }
 
 hipError_t launch_em_relabel(const EmstArgs& a, int src, hipStream_t s) {
-    k_em_relabel<<<em_blocks(a.n, 256), 256, 0, s>>>(a, src);
+    k_em_relabel<<<em_blocks(a.n, kEmPass), kEmPass, 0, s>>>(a, src);
     k_em_copy_comp<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }

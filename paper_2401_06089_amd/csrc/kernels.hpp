@@ -266,18 +266,22 @@ hipError_t launch_fc_label(const FlatArgs& a, int rounds, hipStream_t s);
 // ---- mutual-reachability MST of a point cloud (HDBSCAN*'s first step) ---------------
 constexpr int kEmstMaxDim = 4;
 constexpr int kEmstMaxMinPts = 32;
+constexpr int kEmstPairSlots = 32;   // slots of the examined-pair count (spread against contention)
+// Per-point arrays are indexed by slot: the input index for small clouds,
+// the position in cell order on the grid (sorted[] maps a slot to its input
+// index, which the total order and the output use; slotof[] maps back).
 struct EmstArgs {
     int64_t n;
     int dim, min_pts;
-    const float* pts;          // [n * dim], row-major
+    const float* pts;          // [n * dim], row-major, input order
     double* core2;             // [n] squared core distances
     int32_t* comp;             // [n] component (its root point)
     int32_t* comp2;            // [n] next round's components
     double* best_w;            // [n] least outgoing mrd2 of each point
-    int32_t* best_j;           // [n] its other endpoint (-1: none)
-    int32_t* active;           // [n] points that search again this round
+    int32_t* best_j;           // [n] its other endpoint's slot (-1: none)
+    int32_t* active;           // [n] slots that search again this round
     uint64_t* cmin_w;          // [n] per component root: least mrd2 (bits)
-    uint64_t* cmin_e;          // [n] per component root: least (lo << 32 | hi) at that weight
+    uint64_t* cmin_e;          // [n] per component root: least (lo << 32 | hi) input indices at that weight
     int32_t* parent[2];        // [n] hooking and pointer jumping
     uint64_t* ew;              // [pow2 >= n-1] tree edges: mrd2 bits, endpoints
     int32_t* ea;
@@ -298,14 +302,17 @@ struct EmstArgs {
     int32_t gdim[kEmstMaxDim]; // cells per dimension (1 for unused dimensions)
     int64_t gstride[kEmstMaxDim];
     int64_t ncells;
+    // profiling only: the grid searches add the point pairs they examine
+    // into pairs[block % kEmstPairSlots]
+    int count_pairs;
+    uint64_t* pairs;
     uint32_t* bbox;            // [2 * kEmstMaxDim] order-preserving bits of each min and of each max, complemented
     int32_t* cellof;           // [n] cell of each point
     int32_t* cstart;           // [ncells + 1] first sorted position of each cell
     int32_t* cfill;            // [ncells] points per cell, then a fill counter
-    int32_t* sorted;           // [n] point at each sorted position
+    int32_t* sorted;           // [n] input index at each sorted position (slot)
+    int32_t* slotof;           // [n] slot of each input index
     double* spts;              // [n * kEmstMaxDim] coordinates in sorted order
-    double* score2;            // [n] core distances in sorted order
-    int32_t* scomp;            // [n] components in sorted order (refreshed every round)
     uint8_t* partial;          // [n] the point's search stopped early: search again next round
     uint64_t* scan_agg;        // cell-count scan: per-block sums
 };
@@ -319,7 +326,6 @@ hipError_t launch_em_sort_out(const EmstArgs& a, int64_t len, hipStream_t s);
 hipError_t launch_em_bbox(const EmstArgs& a, hipStream_t s);
 hipError_t launch_em_grid(const EmstArgs& a, hipStream_t s);         // cells, counts, scan, scatter
 hipError_t launch_em_core_grid(const EmstArgs& a, hipStream_t s);      // leftovers listed in fallback
-hipError_t launch_em_sorted_state(const EmstArgs& a, int with_core, hipStream_t s);
 hipError_t launch_em_search_grid(const EmstArgs& a, int64_t active, hipStream_t s);
 
 // ---- misc -----------------------------------------------------------------------

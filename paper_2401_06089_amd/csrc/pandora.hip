@@ -287,6 +287,18 @@ hipError_t timed(int kind, double bytes, hipStream_t s, F&& launch) {
     return e;
 }
 
+// Adds work counted on the device to a kind's algorithmic total (its
+// launches are timed separately).
+void profile_add(int kind, double amount) {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    if (!t_capturing && (g_prof.mask & (1u << kind))) g_prof.bytes[kind] += amount;
+}
+
+bool profiling(int kind) {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    return !t_capturing && (g_prof.mask & (1u << kind));
+}
+
 // Called once the stream has been synchronized.
 void drain_profile() {
     if (t_pending.empty()) return;
@@ -1011,14 +1023,15 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
 // ---- mutual-reachability MST of a point cloud -------------------------------------
 
 struct EmstLayout {
-    size_t core2, comp, comp2, best_w, best_j, active, cmin_w, cmin_e, par0, par1, ew, ea, eb, counters, bbox,
-        cellof, cstart, cfill, sorted, spts, score2, scomp, partial, fallback, scan_agg;
+    size_t core2, comp, comp2, best_w, best_j, active, cmin_w, cmin_e, par0, par1, ew, ea, eb, counters, pairs, bbox,
+        cellof, cstart, cfill, sorted, slotof, spts, partial, fallback, scan_agg;
     int64_t len = 0;        // padded edge-list length (a power of two >= n - 1)
     int64_t max_cells = 0;  // grid cells allowed
     size_t total = 0;
 };
 
-constexpr int64_t kEmstGridMin = 2048;   // clouds at least this large use the grid
+constexpr int64_t kEmstGridMin = 2048;
+constexpr size_t kPairsHostAt = 256;     // pinned readback of the pair counts, after the counters   // clouds at least this large use the grid
 
 EmstLayout make_emst_layout(int64_t n) {
     EmstLayout E;
@@ -1041,14 +1054,14 @@ EmstLayout make_emst_layout(int64_t n) {
     E.ea = take(c, 4 * E.len);
     E.eb = take(c, 4 * E.len);
     E.counters = take(c, 32);
+    E.pairs = take(c, 8 * kEmstPairSlots);
     E.bbox = take(c, 8 * kEmstMaxDim);
     E.cellof = take(c, grid ? 4 * n : 0);
     E.cstart = take(c, grid ? 4 * (E.max_cells + 1) : 0);
     E.cfill = take(c, grid ? 4 * E.max_cells : 0);
     E.sorted = take(c, grid ? 4 * n : 0);
     E.spts = take(c, grid ? 8 * kEmstMaxDim * n : 0);
-    E.score2 = take(c, grid ? 8 * n : 0);
-    E.scomp = take(c, grid ? 4 * n : 0);
+    E.slotof = take(c, grid ? 4 * n : 0);
     E.partial = take(c, grid ? n : 0);
     E.fallback = take(c, grid ? 4 * n : 0);
     E.scan_agg = take(c, grid ? 8 * ((E.max_cells + 4095) / 4096 + 1) : 0);
@@ -1121,7 +1134,7 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
     Workspace& ws = *workspace_for(dev, s);
     std::lock_guard<std::mutex> lock(ws.mu);
     const EmstLayout E = make_emst_layout(n);
-    int rc = ensure(ws, E.total, host_bytes_for(1));
+    int rc = ensure(ws, E.total, std::max<size_t>(host_bytes_for(1), kPairsHostAt + 8 * kEmstPairSlots));
     if (rc != PANDORA_OK) return rc;
     void* d = ws.dev;
     EmstArgs a{};
@@ -1157,9 +1170,25 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
     PD_TRY(launch_clear_words(a.counters, 8, s));
 
     // The searches are dense fp64 work: their "bytes" in the profiler are
-    // fp64 operations, 3 per coordinate and 2 more per point pair examined
-    // (for the grid, the pairs of a full sweep).
-    const double pair_ops = (double)n * (double)n * (3.0 * dim + 2.0);
+    // fp64 operations, 3 per coordinate and 2 more per point pair examined.
+    // The sweeps examine every pair; the grid searches count theirs on the
+    // device while the profiler watches them.
+    const double ops_per_pair = 3.0 * dim + 2.0;
+    const double pair_ops = (double)n * (double)n * ops_per_pair;
+    a.pairs = at<uint64_t>(d, E.pairs);
+    a.count_pairs = (profiling(PK_EM_CORE) || profiling(PK_EM_SEARCH)) ? 1 : 0;
+    auto counted_pairs = [&](int kind) -> int {
+        if (!a.count_pairs) return PANDORA_OK;
+        uint64_t* hp = reinterpret_cast<uint64_t*>(static_cast<char*>(ws.host) + kPairsHostAt);
+        PD_TRY(hipMemcpyAsync(hp, a.pairs, 8 * kEmstPairSlots, hipMemcpyDeviceToHost, s));
+        PD_TRY(hipStreamSynchronize(s));
+        double total = 0.0;
+        for (int k = 0; k < kEmstPairSlots; ++k) total += (double)hp[k];
+        profile_add(kind, total * ops_per_pair);
+        PD_TRY(launch_clear_words(reinterpret_cast<uint32_t*>(a.pairs), 2 * kEmstPairSlots, s));
+        return PANDORA_OK;
+    };
+    if (a.count_pairs) PD_TRY(launch_clear_words(reinterpret_cast<uint32_t*>(a.pairs), 2 * kEmstPairSlots, s));
     if (E.max_cells > 0) {
         PD_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(a.bbox), 2 * kEmstMaxDim, -1, s));
         PD_TRY(launch_em_bbox(a, s));
@@ -1175,19 +1204,19 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
         a.cfill = at<int32_t>(d, E.cfill);
         a.sorted = at<int32_t>(d, E.sorted);
         a.spts = at<double>(d, E.spts);
-        a.score2 = at<double>(d, E.score2);
-        a.scomp = at<int32_t>(d, E.scomp);
+        a.slotof = at<int32_t>(d, E.slotof);
         a.partial = at<uint8_t>(d, E.partial);
         a.fallback = at<int32_t>(d, E.fallback);
         a.scan_agg = at<uint64_t>(d, E.scan_agg);
         PD_TRY(launch_clear_words(reinterpret_cast<uint32_t*>(a.cfill), a.ncells, s));
         PD_TRY(launch_em_grid(a, s));
-        PD_TIMED(PK_EM_CORE, pair_ops, launch_em_core_grid(a, s));
+        PD_TIMED(PK_EM_CORE, 0.0, launch_em_core_grid(a, s));
         int rc2 = read_counters();
         if (rc2 != PANDORA_OK) return rc2;
         if (hc[2]) return (hc[2] & 1u) ? PANDORA_ERR_INVALID_ARG : PANDORA_ERR_HIP;
-        PD_TIMED(PK_EM_CORE, 0.0, launch_em_core(a, a.fallback, hc[4], s));
-        PD_TRY(launch_em_sorted_state(a, 1, s));
+        rc2 = counted_pairs(PK_EM_CORE);
+        if (rc2 != PANDORA_OK) return rc2;
+        PD_TIMED(PK_EM_CORE, (double)hc[4] * pair_ops / (double)n, launch_em_core(a, a.fallback, hc[4], s));
     } else {
         PD_TIMED(PK_EM_CORE, pair_ops, launch_em_core(a, nullptr, 0, s));
     }
@@ -1202,13 +1231,14 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
         const int64_t active = hc[3];
         if (active > n) return PANDORA_ERR_HIP;
         if (a.use_grid) {
-            PD_TRY(launch_em_sorted_state(a, 0, s));
-            PD_TIMED(PK_EM_SEARCH, pair_ops, launch_em_search_grid(a, active, s));
+            PD_TIMED(PK_EM_SEARCH, 0.0, launch_em_search_grid(a, active, s));
             rc2 = read_counters();
             if (rc2 != PANDORA_OK) return rc2;
             const int64_t left = hc[4];
             if (left > active) return PANDORA_ERR_HIP;
-            PD_TIMED(PK_EM_SEARCH, 0.0, launch_em_search(a, a.fallback, left, s));
+            rc2 = counted_pairs(PK_EM_SEARCH);
+            if (rc2 != PANDORA_OK) return rc2;
+            PD_TIMED(PK_EM_SEARCH, (double)left * pair_ops / (double)n, launch_em_search(a, a.fallback, left, s));
         } else {
             PD_TIMED(PK_EM_SEARCH, (double)active * (double)n * (3.0 * dim + 2.0),
                      launch_em_search(a, a.active, active, s));
