@@ -13,17 +13,19 @@
 // Borůvka rounds: every point finds its least edge to another component.
 // Small clouds sweep all points in LDS tiles (dense fp64 vector work, no
 // matrix-core shape); clouds of 2,048+ points search a uniform grid ring by
-// ring, stop at exact distance bounds (or at an edge the point's component
-// already has that it cannot beat), and leave isolated points to a full
-// sweep.  On the grid every per-point array is kept in cell order (a point's
-// slot), so that the passes over all points read and write them in order
-// and a search's neighbours sit next to it.  A point whose previous least
-// edge still leaves its component keeps it.  Components take the least edge of their points
-// (two atomic minima: weight bits, then endpoints), hook along it (a
-// mutual pair keeps the smaller root), and pointer jumping relabels.  Each
-// round at least halves the components.  The tree's edges are then sorted
-// by the total order (bitonic network) and handed out with fp64 and fp32
-// weights.
+// ring, stop at exact distance bounds, and leave isolated points to a full
+// sweep.  A search also stops once no farther point can beat an edge its
+// component already has; the point then keeps the distance bound it reached
+// as a lower bound on its least edge, and later rounds skip it while its
+// component has a lighter edge.  On the grid every per-point array is kept
+// in cell order (a point's slot), so that the passes over all points read
+// and write them in order and a search's neighbours sit next to it.  A point
+// whose previous least edge still leaves its component keeps it.
+// Components take the least edge of their points (two atomic minima: weight
+// bits, then endpoints), hook along it (a mutual pair keeps the smaller
+// root), and pointer jumping relabels.  Each round at least halves the
+// components.  The tree's edges are then sorted by the total order (bitonic
+// network) and handed out with fp64 and fp32 weights.
 #include "kernels.hpp"
 
 namespace pandora {
@@ -740,11 +742,20 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
     const int32_t mc = a.comp[i];
     double bw = INFINITY;
     int32_t blo = INT32_MAX, bhi = INT32_MAX, bj = -1;
-    bool partial = false, done = !live;
+    bool partial = false, done = !live, unchanged = false;
+    double lower = 0.0;                                   // after an early stop: least edge >= lower
     uint32_t pairs = 0;
+    // An earlier early stop left a lower bound on this point's least edge,
+    // which still holds (the candidates only lose points as components
+    // grow): if its component already has a lighter edge, nothing to do.
+    if (live && a.partial[i]) {
+        const double L = a.best_w[i];
+        const uint64_t cb = __hip_atomic_load(&a.cmin_w[mc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cb != ~0ull && L > __longlong_as_double((long long)cb)) unchanged = partial = done = true;
+    }
     const int rmax = max_ring(a);
     const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
-    for (int r = 0; live && r <= rcap; ++r) {
+    for (int r = 0; !done && r <= rcap; ++r) {
         for_ring(a, c, r, [&](int32_t p0, int32_t p1) {
             for (int32_t p = p0; p < p1; ++p) {
                 if (a.comp[p] == mc) continue;
@@ -769,23 +780,23 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
         }
         const uint64_t cb = __hip_atomic_load(&a.cmin_w[mc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cb != ~0ull && lb2 > __longlong_as_double((long long)cb)) {
-            partial = true;                                   // stopped early
+            partial = true;                                   // stopped early: bw >= lb2 > cb
+            lower = lb2;
             done = true;
             break;
         }
     }
-    const bool report = live && done;
     if (live && !done) {                                  // far from other components: full sweep
         a.partial[i] = 0;
         const uint32_t k = atomicAdd(&a.counters[4], 1u);
         a.fallback[k] = i;
     }
-    if (report) {
-        a.best_w[i] = bw;
-        a.best_j[i] = bj;
+    if (live && done && !unchanged) {
+        a.best_w[i] = partial ? lower : bw;               // a partial point holds its lower bound
+        a.best_j[i] = partial ? -1 : bj;
         a.partial[i] = partial ? 1 : 0;
     }
-    wave_min_into(a.cmin_w, mc, (uint64_t)__double_as_longlong(bw), report && bj >= 0);
+    wave_min_into(a.cmin_w, mc, (uint64_t)__double_as_longlong(bw), live && done && !partial && bj >= 0);
     if (a.count_pairs) wave_count(a.pairs, pairs);
 }
 
