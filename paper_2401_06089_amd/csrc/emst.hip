@@ -33,7 +33,7 @@ namespace pandora {
 namespace {
 
 constexpr int kEmBlock = 256;
-constexpr int kEmMaxK = kEmstMaxMinPts - 1;       // core-distance rank held in registers
+constexpr int kEmMaxK = kEmstMaxMinPts - 1;       // core-distance rank held in registers (at most)
 constexpr int kGridRingCap = 4;                    // rings searched in the grid before a full sweep
 
 __device__ __forceinline__ double d2_of(const double* a, const double* b, int dim) {
@@ -134,6 +134,7 @@ constexpr int kEmPass = 1024;    // block of the passes over all points that app
 // registers (sorted, fully unrolled so that nothing spills).
 // With a list, only the listed slots (the grid search's leftovers), and
 // nothing but their core distance is written.
+template <int KMAX>
 __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t* list, int64_t count) {
     __shared__ double s_p[kEmBlock][kEmstMaxDim];
     const int64_t slot = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
@@ -149,9 +150,9 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t*
             bad |= !isfinite(me[k]);
         }
     }
-    double top[kEmMaxK];
+    double top[KMAX];
 #pragma unroll
-    for (int t = 0; t < kEmMaxK; ++t) top[t] = INFINITY;
+    for (int t = 0; t < KMAX; ++t) top[t] = INFINITY;
     double thr = INFINITY;                                // top[K-1], kept in a register
     for (int64_t j0 = 0; j0 < a.n; j0 += kEmBlock) {
         __syncthreads();
@@ -169,17 +170,17 @@ __global__ __launch_bounds__(kEmBlock) void k_em_core(EmstArgs a, const int32_t*
             // insert d into the sorted list and drop the largest (constant
             // indices only, so the list stays in registers)
 #pragma unroll
-            for (int t = kEmMaxK - 1; t >= 1; --t) top[t] = fmin(top[t], fmax(top[t - 1], d));
+            for (int t = KMAX - 1; t >= 1; --t) top[t] = fmin(top[t], fmax(top[t - 1], d));
             top[0] = fmin(top[0], d);
 #pragma unroll
-            for (int t = 0; t < kEmMaxK; ++t)
+            for (int t = 0; t < KMAX; ++t)
                 if (t == K - 1) thr = top[t];
         }
     }
     if (i < a.n) {
         double c = 0.0;
 #pragma unroll
-        for (int t = 0; t < kEmMaxK; ++t)
+        for (int t = 0; t < KMAX; ++t)
             if (t == K - 1) c = top[t];
         a.core2[i] = c;
         if (!list) {
@@ -611,25 +612,48 @@ __global__ void k_em_scatter(EmstArgs a) {
 }
 
 // Visits the cells of Chebyshev ring r around cell coordinates c (only cells
-// inside the grid); f(first, last) gets each cell's sorted positions.
+// inside the grid) of the point at me; f(first, last, b2) gets each cell's
+// sorted positions and a lower bound b2 on the squared distance from me to
+// any point placed in the cell: the distance to the cell's box, less twice
+// the placement slack per coordinate, squared and shrunk against its own
+// rounding.
 template <class F>
-__device__ __forceinline__ void for_ring(const EmstArgs& a, const int32_t* c, int r, F&& f) {
-    const int side = 2 * r + 1;
-    int64_t combos = 1;
-    for (int k = 0; k < a.dim; ++k) combos *= side;
-    for (int64_t t = 0; t < combos; ++t) {
-        int64_t rest = t, cell = 0;
+__device__ __forceinline__ void for_ring(const EmstArgs& a, const int32_t* c, const double* me, int r, F&& f) {
+    // offsets d[k] in [-r, r] counted like an odometer (constant indices
+    // only, so that nothing leaves the registers, and no 64-bit division)
+    int d[kEmstMaxDim];
+#pragma unroll
+    for (int k = 0; k < kEmstMaxDim; ++k) d[k] = k < a.dim ? -r : 0;
+    for (;;) {
+        int64_t cell = 0;
         bool inside = true, shell = false;
-        for (int k = 0; k < a.dim; ++k) {
-            const int d = (int)(rest % side) - r;
-            rest /= side;
-            shell |= (d == r || d == -r);
-            const int64_t ck = (int64_t)c[k] + d;
-            inside &= ck >= 0 && ck < a.gdim[k];
-            cell += ck * a.gstride[k];
+        double b2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kEmstMaxDim; ++k) {
+            if (k < a.dim) {
+                shell |= (d[k] == r || d[k] == -r);
+                const int32_t ck = c[k] + d[k];
+                inside &= ck >= 0 && ck < a.gdim[k];
+                cell += (int64_t)ck * a.gstride[k];
+                const double lo = a.gmin[k] + (double)ck * a.h;
+                const double gap = fmax(lo - me[k], me[k] - (lo + a.h)) - 2.0 * a.gslack;
+                b2 += gap > 0.0 ? gap * gap : 0.0;
+            }
         }
-        if (!inside || !(shell || r == 0)) continue;
-        f(a.cstart[cell], a.cstart[cell + 1]);
+        if (inside && (shell || r == 0)) f(a.cstart[cell], a.cstart[cell + 1], b2 * (1.0 - 1e-12));
+        bool carry = true;
+#pragma unroll
+        for (int k = 0; k < kEmstMaxDim; ++k) {
+            if (carry && k < a.dim) {
+                if (d[k] < r) {
+                    ++d[k];
+                    carry = false;
+                } else {
+                    d[k] = -r;
+                }
+            }
+        }
+        if (carry) break;
     }
 }
 
@@ -652,6 +676,7 @@ __device__ __forceinline__ int max_ring(const EmstArgs& a) {
 // Core distances by widening rings: stop once the K-th smallest is no more
 // than the bound for everything farther out.
 // Returns the pairs examined.
+template <int KMAX>
 __device__ __forceinline__ uint32_t core_grid_point(const EmstArgs& a, int64_t i) {
     const int K = a.min_pts - 1;
     double me[kEmstMaxDim];
@@ -668,9 +693,9 @@ __device__ __forceinline__ uint32_t core_grid_point(const EmstArgs& a, int64_t i
         }
     }
     if (bad) atomicOr(&a.counters[2], 1u);
-    double top[kEmMaxK];
+    double top[KMAX];
 #pragma unroll
-    for (int t = 0; t < kEmMaxK; ++t) top[t] = INFINITY;
+    for (int t = 0; t < KMAX; ++t) top[t] = INFINITY;
     double thr = INFINITY;
     uint32_t pairs = 0;
     bool done = K == 0;
@@ -678,17 +703,18 @@ __device__ __forceinline__ uint32_t core_grid_point(const EmstArgs& a, int64_t i
         const int rmax = max_ring(a);
         const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
         for (int r = 0; r <= rcap; ++r) {
-            for_ring(a, c, r, [&](int32_t p0, int32_t p1) {
+            for_ring(a, c, me, r, [&](int32_t p0, int32_t p1, double b2) {
+                if (b2 >= thr) return;                    // nothing in the cell can enter the list
                 for (int32_t p = p0; p < p1; ++p) {
                     if (p == i) continue;
                     const double d = d2_of(me, a.spts + (int64_t)p * kEmstMaxDim, a.dim);
                     ++pairs;
                     if (d >= thr) continue;
 #pragma unroll
-                    for (int t = kEmMaxK - 1; t >= 1; --t) top[t] = fmin(top[t], fmax(top[t - 1], d));
+                    for (int t = KMAX - 1; t >= 1; --t) top[t] = fmin(top[t], fmax(top[t - 1], d));
                     top[0] = fmin(top[0], d);
 #pragma unroll
-                    for (int t = 0; t < kEmMaxK; ++t)
+                    for (int t = 0; t < KMAX; ++t)
                         if (t == K - 1) thr = top[t];
                 }
             });
@@ -704,7 +730,7 @@ __device__ __forceinline__ uint32_t core_grid_point(const EmstArgs& a, int64_t i
     }
     double core = 0.0;
 #pragma unroll
-    for (int t = 0; t < kEmMaxK; ++t)
+    for (int t = 0; t < KMAX; ++t)
         if (t == K - 1) core = top[t];
     a.core2[i] = core;
     a.comp[i] = (int32_t)i;
@@ -715,9 +741,10 @@ __device__ __forceinline__ uint32_t core_grid_point(const EmstArgs& a, int64_t i
     return pairs;
 }
 
+template <int KMAX>
 __global__ __launch_bounds__(kEmBlock) void k_em_core_grid(EmstArgs a) {
     const int64_t q = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;   // sorted position: cell order
-    const uint32_t pairs = q < a.n ? core_grid_point(a, q) : 0u;
+    const uint32_t pairs = q < a.n ? core_grid_point<KMAX>(a, q) : 0u;
     if (a.count_pairs) wave_count(a.pairs, pairs);
 }
 
@@ -756,7 +783,8 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
     const int rmax = max_ring(a);
     const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
     for (int r = 0; !done && r <= rcap; ++r) {
-        for_ring(a, c, r, [&](int32_t p0, int32_t p1) {
+        for_ring(a, c, me, r, [&](int32_t p0, int32_t p1, double b2) {
+            if (b2 > bw) return;                              // nothing in the cell can beat bw
             for (int32_t p = p0; p < p1; ++p) {
                 if (a.comp[p] == mc) continue;
                 const double d = d2_of(me, a.spts + (int64_t)p * kEmstMaxDim, a.dim);
@@ -804,9 +832,32 @@ inline unsigned em_blocks(int64_t n, int per) { return (unsigned)((n + per - 1) 
 
 }  // namespace
 
+// The list of the K smallest squared distances lives in registers: its
+// capacity is the next of 1, 3, 7, 15, 31 at or above K = min_pts - 1.
+template <template <int> class Launch, class... Args>
+void with_core_capacity(int K, Args&&... args) {
+    if (K <= 1) Launch<1>::run(args...);
+    else if (K <= 3) Launch<3>::run(args...);
+    else if (K <= 7) Launch<7>::run(args...);
+    else if (K <= 15) Launch<15>::run(args...);
+    else Launch<kEmMaxK>::run(args...);
+}
+template <int KMAX>
+struct CoreSweep {
+    static void run(const EmstArgs& a, const int32_t* list, int64_t count, int64_t m, hipStream_t s) {
+        k_em_core<KMAX><<<em_blocks(m, kEmBlock), kEmBlock, 0, s>>>(a, list, count);
+    }
+};
+template <int KMAX>
+struct CoreGrid {
+    static void run(const EmstArgs& a, hipStream_t s) {
+        k_em_core_grid<KMAX><<<em_blocks(a.n, kEmBlock), kEmBlock, 0, s>>>(a);
+    }
+};
+
 hipError_t launch_em_core(const EmstArgs& a, const int32_t* list, int64_t count, hipStream_t s) {
     const int64_t m = list ? count : a.n;
-    if (m > 0) k_em_core<<<em_blocks(m, kEmBlock), kEmBlock, 0, s>>>(a, list, count);
+    if (m > 0) with_core_capacity<CoreSweep>(a.min_pts - 1, a, list, count, m, s);
     return hipGetLastError();
 }
 
@@ -842,7 +893,7 @@ hipError_t launch_em_grid(const EmstArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_em_core_grid(const EmstArgs& a, hipStream_t s) {
-    k_em_core_grid<<<em_blocks(a.n, kEmBlock), kEmBlock, 0, s>>>(a);
+    with_core_capacity<CoreGrid>(a.min_pts - 1, a, s);
     return hipGetLastError();
 }
 

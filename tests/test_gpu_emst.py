@@ -49,7 +49,7 @@ def test_matches_oracle(dim, min_pts):
 
 
 @pytest.mark.parametrize("dim", [1, 2, 3, 4])
-@pytest.mark.parametrize("min_pts", [1, 3, 16])
+@pytest.mark.parametrize("min_pts", [1, 2, 3, 6, 16, 32])
 def test_grid_search_matches_oracle(dim, min_pts):
     """Clouds of at least 2,048 points take the uniform-grid search (rings,
     early stops, full sweeps for far points)."""
