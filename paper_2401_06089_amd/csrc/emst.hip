@@ -757,15 +757,6 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
     const int64_t slot = (int64_t)blockIdx.x * kEmBlock + threadIdx.x;
     const bool live = slot < count;
     const int32_t i = live ? a.active[slot] : 0;
-    const int32_t io = a.sorted[i];
-    double me[kEmstMaxDim];
-    int32_t c[kEmstMaxDim];
-#pragma unroll
-    for (int k = 0; k < kEmstMaxDim; ++k) {
-        me[k] = k < a.dim ? a.spts[(int64_t)i * kEmstMaxDim + k] : 0.0;
-        c[k] = k < a.dim ? cell_coord(a, me[k], k) : 0;
-    }
-    const double ci = a.core2[i];
     const int32_t mc = a.comp[i];
     double bw = INFINITY;
     int32_t blo = INT32_MAX, bhi = INT32_MAX, bj = -1;
@@ -780,6 +771,15 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
         const uint64_t cb = __hip_atomic_load(&a.cmin_w[mc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cb != ~0ull && L > __longlong_as_double((long long)cb)) unchanged = partial = done = true;
     }
+    const int32_t io = done ? 0 : a.sorted[i];
+    double me[kEmstMaxDim];
+    int32_t c[kEmstMaxDim];
+#pragma unroll
+    for (int k = 0; k < kEmstMaxDim; ++k) {
+        me[k] = (k < a.dim && !done) ? a.spts[(int64_t)i * kEmstMaxDim + k] : 0.0;
+        c[k] = k < a.dim ? cell_coord(a, me[k], k) : 0;
+    }
+    const double ci = done ? 0.0 : a.core2[i];
     const int rmax = max_ring(a);
     const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
     for (int r = 0; !done && r <= rcap; ++r) {

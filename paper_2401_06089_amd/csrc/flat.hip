@@ -376,33 +376,60 @@ __global__ void k_fc_prepare(FlatArgs a) {
     if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&a.counters[1], 1u);
 }
 
+// fp64 sum of val into base[key] for the lanes with act.  Lanes that share
+// the first active lane's key (edges of one large cluster, usually) send
+// one combined sum.  Every lane of the wave must call it.
+__device__ void wave_add_into(double* base, int32_t key, double val, bool act) {
+    const uint64_t m = ballot(act);
+    if (!m) return;
+    const int leader = __ffsll((long long)m) - 1;
+    const int32_t k0 = __shfl(key, leader, kWave);
+    const bool same = act && key == k0;
+    double v = same ? val : 0.0;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    if (lane_id() == leader) unsafeAtomicAdd(&base[k0], v);
+    if (act && !same) unsafeAtomicAdd(&base[key], val);
+}
+
 // Departure terms count * lambda per edge node of a cluster region, the birth
 // term -size * lambda_birth, and each born cluster's parent cluster.
 __global__ void k_fc_stab(FlatArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int32_t root = (int32_t)a.m;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.m; e += stride) {
-        const int32_t sz = a.size[e];
-        if (sz < a.mcs) continue;
-        const int32_t c = a.T[e];
-        if (c < 0 || c > root) {
-            atomicOr(&a.counters[1], 2u);
-            continue;
-        }
-        const int32_t d = a.bigcnt[e] == 1u ? sz - a.bigmax[e] : sz;
-        const double lam = 1.0 / (double)a.w[e];
-        if (c != root) unsafeAtomicAdd(&a.stab[c], (double)d * lam);
-        if (c == (int32_t)e) {
-            const int32_t p = a.ep[e];                        // a born edge always has a parent
-            if (p < 0 || p >= a.m) {
+    const int lane = lane_id();
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); e0 < a.m; e0 += stride) {
+        const int64_t e = e0 + lane;
+        int32_t c = -1;
+        double term = 0.0;
+        bool born = false;
+        const int32_t sz = e < a.m ? a.size[e] : 0;
+        if (e < a.m && sz >= a.mcs) {
+            const int32_t ce = a.T[e];
+            if (ce < 0 || ce > root) {
                 atomicOr(&a.counters[1], 2u);
-                continue;
+            } else {
+                const int32_t d = a.bigcnt[e] == 1u ? sz - a.bigmax[e] : sz;
+                if (ce != root) {
+                    c = ce;
+                    term = (double)d * (1.0 / (double)a.w[e]);
+                }
+                if (ce == (int32_t)e) {
+                    const int32_t p = a.ep[e];                // a born edge always has a parent
+                    if (p < 0 || p >= a.m) {
+                        atomicOr(&a.counters[1], 2u);
+                    } else {
+                        const double lamb = 1.0 / (double)a.w[p];
+                        unsafeAtomicAdd(&a.stab[e], -((double)sz * lamb));
+                        a.cpar[e] = a.T[p];
+                        born = true;
+                    }
+                }
             }
-            const double lamb = 1.0 / (double)a.w[p];
-            unsafeAtomicAdd(&a.stab[e], -((double)sz * lamb));
-            a.cpar[e] = a.T[p];
-            atomicAdd(&a.counters[0], 1u);
         }
+        wave_add_into(a.stab, c, term, c >= 0);
+        const uint64_t b = ballot(born);
+        if (b != 0 && lane == __ffsll((long long)b) - 1) atomicAdd(&a.counters[0], (uint32_t)popc64(b));
     }
 }
 
@@ -644,7 +671,9 @@ __global__ void k_fc_label(FlatArgs a, int src) {
             const int leader = __ffsll((long long)open) - 1;
             const int32_t l = __shfl(lab, leader, kWave);
             const uint64_t same = ballot(mine && lab == l);
-            if (lane == leader) atomicMin(&a.minv[l], (int32_t)x);
+            // a load first: with a few huge clusters most atomics would change nothing
+            if (lane == leader && (int32_t)x < __hip_atomic_load(&a.minv[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMin(&a.minv[l], (int32_t)x);
             open &= ~same;
         }
     }
