@@ -24,8 +24,9 @@
 // Components take the least edge of their points (two atomic minima: weight
 // bits, then endpoints), hook along it (a mutual pair keeps the smaller
 // root), and pointer jumping relabels.  Each round at least halves the
-// components.  The tree's edges are then sorted by the total order (bitonic
-// network) and handed out with fp64 and fp32 weights.
+// components.  The tree's edges are then sorted by the total order (the
+// library's stable LSD radix passes, one 32-bit key word at a time) and
+// handed out with fp64 and fp32 weights.
 #include "kernels.hpp"
 
 namespace pandora {
@@ -349,76 +350,24 @@ __global__ void k_em_copy_comp(EmstArgs a) {
     if (i < a.n) a.comp[i] = a.comp2[i];
 }
 
-// One compare-exchange step of a bitonic sorting network over the padded
-// edge list (keys: weight bits, then the two endpoints).
-__global__ void k_em_bitonic(EmstArgs a, int64_t len, int64_t k, int64_t j) {
+// Keys of the radix sort of the tree's edges, one 32-bit word per sort,
+// from the least significant word of the total order's key: 0 = the larger
+// endpoint, 1 = the smaller, 2 and 3 = the low and high halves of the mrd2
+// bits (non-negative doubles order like their bits).  keys[i] = that word of
+// edge order[i]; with order == nullptr the order is the identity, which is
+// then written to order_out.
+__global__ void k_em_sort_key(EmstArgs a, int word, const int32_t* order, uint32_t* keys, int32_t* order_out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= len) return;
-    const int64_t l = i ^ j;
-    if (l <= i) return;
-    const bool up = (i & k) == 0;
-    const uint64_t wi = a.ew[i], wl = a.ew[l];
-    const int32_t ai = a.ea[i], al = a.ea[l], bi = a.eb[i], bl = a.eb[l];
-    const bool gt = wi > wl || (wi == wl && (ai > al || (ai == al && bi > bl)));
-    if (gt == up) {
-        a.ew[i] = wl;
-        a.ew[l] = wi;
-        a.ea[i] = al;
-        a.ea[l] = ai;
-        a.eb[i] = bl;
-        a.eb[l] = bi;
-    }
-}
-
-// The steps with partner distance j < kSortTile stay inside one tile of
-// consecutive elements: a workgroup does all of them for a stage k in LDS
-// (k <= 0 runs every stage up to kSortTile, i.e. sorts each tile).
-constexpr int kSortTile = 2048;
-__global__ __launch_bounds__(kSortTile / 2) void k_em_bitonic_tile(EmstArgs a, int64_t kstage) {
-    __shared__ uint64_t s_w[kSortTile];
-    __shared__ int32_t s_a[kSortTile], s_b[kSortTile];
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int t = threadIdx.x; t < kSortTile; t += blockDim.x) {
-        s_w[t] = a.ew[base + t];
-        s_a[t] = a.ea[base + t];
-        s_b[t] = a.eb[base + t];
-    }
-    __syncthreads();
-    const int64_t k_lo = kstage > 0 ? kstage : 2, k_hi = kstage > 0 ? kstage : kSortTile;
-    for (int64_t k = k_lo; k <= k_hi; k <<= 1) {
-        for (int64_t j = (k >> 1) < (kSortTile >> 1) ? (k >> 1) : (kSortTile >> 1); j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < kSortTile; t += blockDim.x) {
-                const int l = t ^ (int)j;
-                if (l <= t) continue;
-                const bool up = ((base + t) & k) == 0;
-                const uint64_t wi = s_w[t], wl = s_w[l];
-                const int32_t ai = s_a[t], al = s_a[l], bi = s_b[t], bl = s_b[l];
-                const bool gt = wi > wl || (wi == wl && (ai > al || (ai == al && bi > bl)));
-                if (gt == up) {
-                    s_w[t] = wl;
-                    s_w[l] = wi;
-                    s_a[t] = al;
-                    s_a[l] = ai;
-                    s_b[t] = bl;
-                    s_b[l] = bi;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int t = threadIdx.x; t < kSortTile; t += blockDim.x) {
-        a.ew[base + t] = s_w[t];
-        a.ea[base + t] = s_a[t];
-        a.eb[base + t] = s_b[t];
-    }
-}
-
-__global__ void k_em_pad(EmstArgs a, int64_t from, int64_t len) {
-    const int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= len) return;
-    a.ew[i] = ~0ull;
-    a.ea[i] = INT32_MAX;
-    a.eb[i] = INT32_MAX;
+    if (i >= a.n - 1) return;
+    int32_t e = (int32_t)i;
+    if (order) e = order[i];
+    else order_out[i] = e;
+    uint32_t k;
+    if (word == 0) k = (uint32_t)a.eb[e];
+    else if (word == 1) k = (uint32_t)a.ea[e];
+    else if (word == 2) k = (uint32_t)a.ew[e];
+    else k = (uint32_t)(a.ew[e] >> 32);
+    keys[i] = k;
 }
 
 // Correctly rounded square root.  The device square root is within one unit
@@ -463,13 +412,15 @@ __device__ double sqrt_rn(double x) {
     return y;
 }
 
-__global__ void k_em_out(EmstArgs a) {
+// The k-th edge of the sorted tree is edge order[k] of the recorded list.
+__global__ void k_em_out(EmstArgs a, const int32_t* order) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n - 1) return;
-    const double w2 = __longlong_as_double((long long)a.ew[k]);
+    const int32_t e = order[k];
+    const double w2 = __longlong_as_double((long long)a.ew[e]);
     const double w = sqrt_rn(w2);
-    a.u[k] = a.ea[k];
-    a.v[k] = a.eb[k];
+    a.u[k] = a.ea[e];
+    a.v[k] = a.eb[e];
     if (a.w64) a.w64[k] = w;
     a.w32[k] = __double2float_rn(w);
 }
@@ -913,24 +864,14 @@ hipError_t launch_em_relabel(const EmstArgs& a, int src, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_em_sort_out(const EmstArgs& a, int64_t len, hipStream_t s) {
-    const int64_t m = a.n - 1;
-    if (len > m) k_em_pad<<<em_blocks(len - m, 256), 256, 0, s>>>(a, m, len);
-    if (len < kSortTile) {
-        for (int64_t k = 2; k <= len; k <<= 1)
-            for (int64_t j = k >> 1; j > 0; j >>= 1) k_em_bitonic<<<em_blocks(len, 256), 256, 0, s>>>(a, len, k, j);
-    } else {
-        // tiles first, then per stage: the long-distance steps in global
-        // memory, the rest of the stage inside each tile
-        const unsigned tiles = (unsigned)(len / kSortTile);
-        k_em_bitonic_tile<<<tiles, kSortTile / 2, 0, s>>>(a, 0);
-        for (int64_t k = 2 * kSortTile; k <= len; k <<= 1) {
-            for (int64_t j = k >> 1; j >= kSortTile; j >>= 1)
-                k_em_bitonic<<<em_blocks(len, 256), 256, 0, s>>>(a, len, k, j);
-            k_em_bitonic_tile<<<tiles, kSortTile / 2, 0, s>>>(a, k);
-        }
-    }
-    k_em_out<<<em_blocks(m, 256), 256, 0, s>>>(a);
+hipError_t launch_em_sort_key(const EmstArgs& a, int word, const int32_t* order, uint32_t* keys, int32_t* order_out,
+                              hipStream_t s) {
+    if (a.n > 1) k_em_sort_key<<<em_blocks(a.n - 1, 256), 256, 0, s>>>(a, word, order, keys, order_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_out(const EmstArgs& a, const int32_t* order, hipStream_t s) {
+    if (a.n > 1) k_em_out<<<em_blocks(a.n - 1, 256), 256, 0, s>>>(a, order);
     return hipGetLastError();
 }
 

@@ -283,7 +283,7 @@ struct EmstArgs {
     uint64_t* cmin_w;          // [n] per component root: least mrd2 (bits)
     uint64_t* cmin_e;          // [n] per component root: least (lo << 32 | hi) input indices at that weight
     int32_t* parent[2];        // [n] hooking and pointer jumping
-    uint64_t* ew;              // [pow2 >= n-1] tree edges: mrd2 bits, endpoints
+    uint64_t* ew;              // [n-1] tree edges as recorded: mrd2 bits, endpoints
     int32_t* ea;
     int32_t* eb;
     int32_t* u;                // [n-1] outputs, in (mrd2, u, v) order, u < v
@@ -322,7 +322,9 @@ hipError_t launch_em_search(const EmstArgs& a, const int32_t* list, int64_t coun
 hipError_t launch_em_merge_edges(const EmstArgs& a, hipStream_t s);
 hipError_t launch_em_jump(const EmstArgs& a, int src, hipStream_t s);
 hipError_t launch_em_relabel(const EmstArgs& a, int src, hipStream_t s);
-hipError_t launch_em_sort_out(const EmstArgs& a, int64_t len, hipStream_t s);
+hipError_t launch_em_sort_key(const EmstArgs& a, int word, const int32_t* order, uint32_t* keys, int32_t* order_out,
+                              hipStream_t s);
+hipError_t launch_em_out(const EmstArgs& a, const int32_t* order, hipStream_t s);
 hipError_t launch_em_bbox(const EmstArgs& a, hipStream_t s);
 hipError_t launch_em_grid(const EmstArgs& a, hipStream_t s);         // cells, counts, scan, scatter
 hipError_t launch_em_core_grid(const EmstArgs& a, hipStream_t s);      // leftovers listed in fallback

@@ -1024,8 +1024,10 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
 
 struct EmstLayout {
     size_t core2, comp, comp2, best_w, best_j, active, cmin_w, cmin_e, par0, par1, ew, ea, eb, counters, pairs, bbox,
+        sctrl, skey[2], sval[2], slb[2],
         cellof, cstart, cfill, sorted, slotof, spts, partial, fallback, scan_agg;
-    int64_t len = 0;        // padded edge-list length (a power of two >= n - 1)
+    int64_t len = 0;        // edge-list length (n - 1, at least 1)
+    int64_t slb_words = 0;  // look-back words of one radix pass
     int64_t max_cells = 0;  // grid cells allowed
     size_t total = 0;
 };
@@ -1035,8 +1037,8 @@ constexpr size_t kPairsHostAt = 256;     // pinned readback of the pair counts, 
 
 EmstLayout make_emst_layout(int64_t n) {
     EmstLayout E;
-    E.len = 1;
-    while (E.len < n - 1) E.len <<= 1;
+    E.len = std::max<int64_t>(n - 1, 1);
+    E.slb_words = sort_tiles(E.len, kDefaultSortCfg) << 8;
     E.max_cells = n >= kEmstGridMin ? 4 * n + 16 : 0;
     const bool grid = E.max_cells > 0;
     size_t c = 0;
@@ -1055,6 +1057,12 @@ EmstLayout make_emst_layout(int64_t n) {
     E.eb = take(c, 4 * E.len);
     E.counters = take(c, 32);
     E.pairs = take(c, 8 * kEmstPairSlots);
+    E.sctrl = take(c, sizeof(Control));
+    for (int k = 0; k < 2; ++k) {
+        E.skey[k] = take(c, 4 * E.len);
+        E.sval[k] = take(c, 4 * E.len);
+        E.slb[k] = take(c, 8 * E.slb_words);
+    }
     E.bbox = take(c, 8 * kEmstMaxDim);
     E.cellof = take(c, grid ? 4 * n : 0);
     E.cstart = take(c, grid ? 4 * (E.max_cells + 1) : 0);
@@ -1264,7 +1272,55 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
         comps = hc[1];
     }
     if ((int64_t)hc[0] != n - 1) return PANDORA_ERR_HIP;
-    PD_TIMED(PK_EM_SORT, 32.0 * (double)E.len, launch_em_sort_out(a, E.len, s));
+
+    // The tree in the total order: stable LSD radix sorts of the edge order,
+    // one 32-bit key word at a time from the least significant (endpoint
+    // ids take 3 digits, being below 2^24; the mrd2 halves 4 each).
+    const int64_t m = n - 1;
+    Control* sc = at<Control>(d, E.sctrl);
+    uint32_t* SK[2] = {at<uint32_t>(d, E.skey[0]), at<uint32_t>(d, E.skey[1])};
+    int32_t* SV[2] = {at<int32_t>(d, E.sval[0]), at<int32_t>(d, E.sval[1])};
+    uint64_t* SL[2] = {at<uint64_t>(d, E.slb[0]), at<uint64_t>(d, E.slb[1])};
+    int kc = 0, vc = 0;
+    for (int word = 0; word < 4; ++word) {
+        const int passes = word < 2 ? 3 : 4;
+        PD_TRY(launch_clear_words(reinterpret_cast<uint32_t*>(sc), sizeof(Control) / 4, s));
+        PD_TIMED(PK_EM_SORT, 20.0 * (double)m,
+                 launch_em_sort_key(a, word, word == 0 ? nullptr : SV[vc], SK[kc], SV[vc], s));
+        SortHistArgs h{};
+        h.n = m;
+        h.bits = 8;
+        h.hist_row = 0;
+        h.passes = passes;
+        h.keys = SK[kc];
+        h.lb_zero = SL[0];
+        h.lb_zero_words = E.slb_words;
+        h.ctrl = sc;
+        PD_TIMED(PK_EM_SORT, 4.0 * (double)m, launch_sort_hist(SRC_KEYS, h, s));
+        for (int p = 0; p < passes; ++p) {
+            SortPassArgs pa{};
+            pa.n = m;
+            pa.cfg = kDefaultSortCfg;
+            pa.bits = 8;
+            pa.shift = 8 * p;
+            pa.pass = p;
+            pa.keys_in = SK[kc];
+            pa.vals_in = SV[vc];
+            pa.keys_out = SK[kc ^ 1];
+            pa.vals_out = SV[vc ^ 1];
+            pa.lb = SL[p & 1];
+            pa.lb_zero = SL[(p + 1) & 1];
+            pa.lb_zero_words = E.slb_words;
+            pa.ctrl = sc;
+            PD_TIMED(PK_EM_SORT, 16.0 * (double)m, launch_sort_pass(SRC_KEYS, DST_KEYS, pa, s));
+            kc ^= 1;
+            vc ^= 1;
+        }
+        PD_TRY(hipMemcpyAsync(hc, &sc->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        PD_TRY(hipStreamSynchronize(s));
+        if (hc[0]) return PANDORA_ERR_HIP;
+    }
+    PD_TIMED(PK_EM_SORT, 32.0 * (double)m, launch_em_out(a, SV[vc], s));
     PD_TRY(hipStreamSynchronize(s));
     return PANDORA_OK;
 }
