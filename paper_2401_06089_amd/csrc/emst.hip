@@ -562,39 +562,57 @@ __global__ void k_em_scatter(EmstArgs a) {
     for (int k = 0; k < kEmstMaxDim; ++k) a.spts[pos * kEmstMaxDim + k] = k < a.dim ? (double)a.pts[i * a.dim + k] : 0.0;
 }
 
-// Visits the cells of Chebyshev ring r around cell coordinates c (only cells
-// inside the grid) of the point at me; f(first, last, b2) gets each cell's
-// sorted positions and a lower bound b2 on the squared distance from me to
-// any point placed in the cell: the distance to the cell's box, less twice
-// the placement slack per coordinate, squared and shrunk against its own
-// rounding.
+// Visits the points of Chebyshev ring r around cell coordinates c (only
+// cells inside the grid) of the point at me; ring 1 includes the point's own
+// cell.  Cells are row-major with the first coordinate fastest, so the
+// ring's cells along a row of the first coordinate are one contiguous range
+// of sorted positions: f(first, last, b2) gets such a range (a whole row, or
+// one of a row's two end cells when the row passes through the ring's
+// inside) and a lower bound b2 on the squared distance from me to any point
+// placed in it: the distance to the range's box, less twice the placement
+// slack per coordinate, squared and shrunk against its own rounding.
+__device__ __forceinline__ double gap2(const EmstArgs& a, int k, double x, int32_t c0, int32_t c1) {
+    const double lo = a.gmin[k] + (double)c0 * a.h, hi = a.gmin[k] + (double)(c1 + 1) * a.h;
+    const double gap = fmax(lo - x, x - hi) - 2.0 * a.gslack;
+    return gap > 0.0 ? gap * gap : 0.0;
+}
+
 template <class F>
 __device__ __forceinline__ void for_ring(const EmstArgs& a, const int32_t* c, const double* me, int r, F&& f) {
-    // offsets d[k] in [-r, r] counted like an odometer (constant indices
-    // only, so that nothing leaves the registers, and no 64-bit division)
+    // offsets of coordinates 1.. in [-r, r], counted like an odometer
+    // (constant indices only, so that nothing leaves the registers)
     int d[kEmstMaxDim];
 #pragma unroll
-    for (int k = 0; k < kEmstMaxDim; ++k) d[k] = k < a.dim ? -r : 0;
+    for (int k = 0; k < kEmstMaxDim; ++k) d[k] = (k >= 1 && k < a.dim) ? -r : 0;
+    const int32_t gx = a.gdim[0];
     for (;;) {
-        int64_t cell = 0;
+        int64_t row = 0;
         bool inside = true, shell = false;
         double b2 = 0.0;
 #pragma unroll
-        for (int k = 0; k < kEmstMaxDim; ++k) {
+        for (int k = 1; k < kEmstMaxDim; ++k) {
             if (k < a.dim) {
                 shell |= (d[k] == r || d[k] == -r);
                 const int32_t ck = c[k] + d[k];
                 inside &= ck >= 0 && ck < a.gdim[k];
-                cell += (int64_t)ck * a.gstride[k];
-                const double lo = a.gmin[k] + (double)ck * a.h;
-                const double gap = fmax(lo - me[k], me[k] - (lo + a.h)) - 2.0 * a.gslack;
-                b2 += gap > 0.0 ? gap * gap : 0.0;
+                row += (int64_t)ck * a.gstride[k];
+                b2 += gap2(a, k, me[k], ck, ck);
             }
         }
-        if (inside && (shell || r == 0)) f(a.cstart[cell], a.cstart[cell + 1], b2 * (1.0 - 1e-12));
+        if (inside) {
+            if (shell || r == 1) {                            // the whole row
+                const int32_t x0 = c[0] - r > 0 ? c[0] - r : 0;
+                const int32_t x1 = c[0] + r < gx - 1 ? c[0] + r : gx - 1;
+                f(a.cstart[row + x0], a.cstart[row + x1 + 1], (b2 + gap2(a, 0, me[0], x0, x1)) * (1.0 - 1e-12));
+            } else {                                          // the row's two end cells
+                const int32_t xl = c[0] - r, xr = c[0] + r;
+                if (xl >= 0) f(a.cstart[row + xl], a.cstart[row + xl + 1], (b2 + gap2(a, 0, me[0], xl, xl)) * (1.0 - 1e-12));
+                if (xr < gx) f(a.cstart[row + xr], a.cstart[row + xr + 1], (b2 + gap2(a, 0, me[0], xr, xr)) * (1.0 - 1e-12));
+            }
+        }
         bool carry = true;
 #pragma unroll
-        for (int k = 0; k < kEmstMaxDim; ++k) {
+        for (int k = 1; k < kEmstMaxDim; ++k) {
             if (carry && k < a.dim) {
                 if (d[k] < r) {
                     ++d[k];
@@ -653,7 +671,7 @@ __device__ __forceinline__ uint32_t core_grid_point(const EmstArgs& a, int64_t i
     if (K > 0) {
         const int rmax = max_ring(a);
         const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
-        for (int r = 0; r <= rcap; ++r) {
+        for (int r = 1; r <= rcap; ++r) {
             for_ring(a, c, me, r, [&](int32_t p0, int32_t p1, double b2) {
                 if (b2 >= thr) return;                    // nothing in the cell can enter the list
                 for (int32_t p = p0; p < p1; ++p) {
@@ -733,7 +751,7 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
     const double ci = done ? 0.0 : a.core2[i];
     const int rmax = max_ring(a);
     const int rcap = rmax < kGridRingCap ? rmax : kGridRingCap;
-    for (int r = 0; !done && r <= rcap; ++r) {
+    for (int r = 1; !done && r <= rcap; ++r) {
         for_ring(a, c, me, r, [&](int32_t p0, int32_t p1, double b2) {
             if (b2 > bw) return;                              // nothing in the cell can beat bw
             for (int32_t p = p0; p < p1; ++p) {
