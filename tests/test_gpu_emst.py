@@ -95,3 +95,78 @@ def test_hdbscan_end_to_end(seed, min_pts, mcs):
     assert decisions_safe(info)
     assert np.array_equal(lab.cpu().numpy(), olab)
     assert st.numel() == ost.size >= 2
+
+
+def _exact_d2(x64, i, j):
+    """d2 of the point pairs (i, j), coordinates summed in order, each
+    operation rounded on its own (the definition the oracle uses)."""
+    acc = np.zeros(len(i), np.float64)
+    for k in range(x64.shape[1]):
+        t = x64[i, k] - x64[j, k]
+        acc = acc + t * t
+    return acc
+
+
+@pytest.mark.parametrize("n,min_pts", [(300_000, 2), (300_000, 5)])
+def test_large_cloud_is_a_minimum_spanning_tree(n, min_pts):
+    """Sizes the O(n^2) oracle cannot reach.  A spanning tree (n-1 edges,
+    one component) in weight order; its sorted weights are, entry by entry,
+    at most those of the minimum spanning tree of a candidate graph (every
+    point joined to its 16 nearest neighbours, exact mutual reachability),
+    since a minimum spanning tree minimises every order statistic of its
+    weights; and they are equal when the candidate graph holds a minimum
+    spanning tree, which it does for uniform points in practice."""
+    import paper_2401_06089_amd as pd
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components, minimum_spanning_tree
+    from scipy.spatial import cKDTree
+    x = cloud(n, 3, n + min_pts, "uniform")
+    print(f"emst n={n} min_pts={min_pts} (properties)", flush=True)
+    u, v, w64, w32 = (t.cpu().numpy() for t in pd.emst(torch.from_numpy(x).cuda(), min_pts))
+    assert len(u) == n - 1 and (u < v).all() and (u >= 0).all() and (v < n).all()
+    assert connected_components(coo_matrix((np.ones(n - 1), (u, v)), shape=(n, n)), directed=False)[0] == 1
+    assert (np.diff(w64) >= 0).all() and np.array_equal(w32, w64.astype(np.float32))
+
+    x64 = x.astype(np.float64)
+    k = 16
+    _, nb = cKDTree(x64).query(x64, k=k + 1)
+    ii = np.repeat(np.arange(n), k + 1)
+    jj = nb.reshape(-1)
+    d2 = _exact_d2(x64, ii, jj).reshape(n, k + 1)
+    d2[nb == np.arange(n)[:, None]] = np.inf               # the point itself
+    core2 = np.sort(d2, axis=1)[:, min_pts - 2] if min_pts > 1 else np.zeros(n)
+    keep = jj != ii
+    a, b = ii[keep], jj[keep]
+    mrd2 = np.maximum(np.maximum(core2[a], core2[b]), _exact_d2(x64, a, b))
+    t = minimum_spanning_tree(coo_matrix((mrd2, (a, b)), shape=(n, n)).tocsr()).tocoo()
+    cand = np.sort(np.sqrt(t.data))
+    assert len(cand) == n - 1
+    assert (w64 <= cand).all()
+    assert np.array_equal(w64, cand)
+
+
+def test_full_size_sampled_weights():
+    """10^6 points: tree shape and order, and the weights of sampled edges
+    recomputed exactly (core distances by a pass over every point)."""
+    import paper_2401_06089_amd as pd
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    n, min_pts = 1_000_000, 3
+    x = cloud(n, 3, 77, "uniform")
+    print(f"emst n={n} min_pts={min_pts} (sampled)", flush=True)
+    u, v, w64, w32 = (t.cpu().numpy() for t in pd.emst(torch.from_numpy(x).cuda(), min_pts))
+    assert len(u) == n - 1 and (u < v).all()
+    assert connected_components(coo_matrix((np.ones(n - 1), (u, v)), shape=(n, n)), directed=False)[0] == 1
+    assert (np.diff(w64) >= 0).all() and np.array_equal(w32, w64.astype(np.float32))
+    x64 = x.astype(np.float64)
+    rng = np.random.default_rng(3)
+    allp = np.arange(n)
+
+    def core2(p):
+        d = _exact_d2(x64, np.full(n, p), allp)
+        d[p] = np.inf
+        return np.partition(d, min_pts - 2)[min_pts - 2]
+    for e in rng.integers(0, n - 1, 25):
+        a, b = int(u[e]), int(v[e])
+        mrd2 = max(core2(a), core2(b), float(_exact_d2(x64, np.array([a]), np.array([b]))[0]))
+        assert w64[e] == np.sqrt(mrd2), (e, a, b)
