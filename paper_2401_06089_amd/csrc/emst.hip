@@ -50,6 +50,14 @@ __device__ __forceinline__ double d2_of(const double* a, const double* b, int di
     return acc;
 }
 
+// The same with the second point as stored on the grid: its fp32 input
+// coordinates, four to a 16-byte slot, widened here (exactly).
+__device__ __forceinline__ double d2_of(const double* a, const float* b4, int dim) {
+    const float4 q = *reinterpret_cast<const float4*>(b4);
+    const double b[kEmstMaxDim] = {(double)q.x, (double)q.y, (double)q.z, (double)q.w};
+    return d2_of(a, b, dim);
+}
+
 __device__ __forceinline__ bool key_less(double w, int32_t lo, int32_t hi, double bw, int32_t blo, int32_t bhi) {
     return w < bw || (w == bw && (lo < blo || (lo == blo && hi < bhi)));
 }
@@ -65,7 +73,7 @@ __device__ __forceinline__ int64_t slot_of(const EmstArgs& a, int32_t id) {
 
 // Coordinate k of the point in slot p, widened to fp64.
 __device__ __forceinline__ double coord(const EmstArgs& a, int64_t p, int k) {
-    return a.use_grid ? a.spts[p * kEmstMaxDim + k] : (double)a.pts[p * a.dim + k];
+    return a.use_grid ? (double)a.spts[p * kEmstMaxDim + k] : (double)a.pts[p * a.dim + k];
 }
 
 // Atomic minimum of val into base[key] for the lanes with act.  Lanes that
@@ -559,7 +567,7 @@ __global__ void k_em_scatter(EmstArgs a) {
     a.sorted[pos] = (int32_t)i;
     a.slotof[i] = (int32_t)pos;
 #pragma unroll
-    for (int k = 0; k < kEmstMaxDim; ++k) a.spts[pos * kEmstMaxDim + k] = k < a.dim ? (double)a.pts[i * a.dim + k] : 0.0;
+    for (int k = 0; k < kEmstMaxDim; ++k) a.spts[pos * kEmstMaxDim + k] = k < a.dim ? a.pts[i * a.dim + k] : 0.0f;
 }
 
 // Visits the points of Chebyshev ring r around cell coordinates c (only
@@ -656,7 +664,7 @@ __device__ __forceinline__ uint32_t core_grid_point(const EmstArgs& a, int64_t i
         me[k] = 0.0;
         c[k] = 0;
         if (k < a.dim) {
-            me[k] = a.spts[i * kEmstMaxDim + k];
+            me[k] = (double)a.spts[i * kEmstMaxDim + k];
             bad |= !isfinite(me[k]);
             c[k] = cell_coord(a, me[k], k);
         }
@@ -745,7 +753,7 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best_grid(EmstArgs a, int64_t c
     int32_t c[kEmstMaxDim];
 #pragma unroll
     for (int k = 0; k < kEmstMaxDim; ++k) {
-        me[k] = (k < a.dim && !done) ? a.spts[(int64_t)i * kEmstMaxDim + k] : 0.0;
+        me[k] = (k < a.dim && !done) ? (double)a.spts[(int64_t)i * kEmstMaxDim + k] : 0.0;
         c[k] = k < a.dim ? cell_coord(a, me[k], k) : 0;
     }
     const double ci = done ? 0.0 : a.core2[i];

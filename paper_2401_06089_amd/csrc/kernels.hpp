@@ -312,7 +312,7 @@ struct EmstArgs {
     int32_t* cfill;            // [ncells] points per cell, then a fill counter
     int32_t* sorted;           // [n] input index at each sorted position (slot)
     int32_t* slotof;           // [n] slot of each input index
-    double* spts;              // [n * kEmstMaxDim] coordinates in sorted order
+    float* spts;               // [n * kEmstMaxDim] input coordinates in sorted order (16-byte slots)
     uint8_t* partial;          // [n] the point's search stopped early: search again next round
     uint64_t* scan_agg;        // cell-count scan: per-block sums
 };

@@ -1068,7 +1068,7 @@ EmstLayout make_emst_layout(int64_t n) {
     E.cstart = take(c, grid ? 4 * (E.max_cells + 1) : 0);
     E.cfill = take(c, grid ? 4 * E.max_cells : 0);
     E.sorted = take(c, grid ? 4 * n : 0);
-    E.spts = take(c, grid ? 8 * kEmstMaxDim * n : 0);
+    E.spts = take(c, grid ? 4 * kEmstMaxDim * n : 0);
     E.slotof = take(c, grid ? 4 * n : 0);
     E.partial = take(c, grid ? n : 0);
     E.fallback = take(c, grid ? 4 * n : 0);
@@ -1215,7 +1215,7 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
         a.cstart = at<int32_t>(d, E.cstart);
         a.cfill = at<int32_t>(d, E.cfill);
         a.sorted = at<int32_t>(d, E.sorted);
-        a.spts = at<double>(d, E.spts);
+        a.spts = at<float>(d, E.spts);
         a.slotof = at<int32_t>(d, E.slotof);
         a.partial = at<uint8_t>(d, E.partial);
         a.fallback = at<int32_t>(d, E.fallback);
