@@ -273,6 +273,13 @@ __global__ __launch_bounds__(kEmBlock) void k_em_best(EmstArgs a, const int32_t*
     wave_min_into(a.cmin_w, mc, (uint64_t)__double_as_longlong(bw), i < a.n && bj >= 0);
 }
 
+// The t-th component root of this round (every point in the first round);
+// a.n past the end.
+__device__ __forceinline__ int64_t root_at(const EmstArgs& a, int64_t t) {
+    if (!a.roots) return t < a.n ? t : a.n;
+    return t < a.nroots ? (int64_t)a.roots[t] : a.n;
+}
+
 // Among the points whose edge has the component's least weight, the least endpoints.
 __global__ void k_em_cmin(EmstArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -289,7 +296,8 @@ __global__ void k_em_cmin(EmstArgs a) {
 // Each component hooks to the one across its least edge; of a mutual pair
 // the smaller root stays a root and records the edge once.
 __global__ __launch_bounds__(kEmPass) void k_em_hook(EmstArgs a) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = root_at(a, t);
     bool record = false;
     int32_t lo = 0, hi = 0;
     if (c < a.n && a.comp[c] == (int32_t)c) {
@@ -325,7 +333,8 @@ __global__ __launch_bounds__(kEmPass) void k_em_hook(EmstArgs a) {
 }
 
 __global__ void k_em_jump(EmstArgs a, int src) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = root_at(a, t);
     bool changed = false;
     if (c < a.n && a.comp[c] == (int32_t)c) {
         const int32_t p = a.parent[src][c];
@@ -349,8 +358,8 @@ __global__ __launch_bounds__(kEmPass) void k_em_relabel(EmstArgs a, int src) {
         a.cmin_e[i] = ~0ull;
         root = r == (int32_t)i;
     }
-    const int roots = __syncthreads_count(root);
-    if (threadIdx.x == 0 && roots) atomicAdd(&a.counters[1], (uint32_t)roots);
+    const uint32_t k = block_append<kEmPass>(&a.counters[1], root);
+    if (root) a.roots_next[k] = (int32_t)i;
 }
 
 __global__ void k_em_copy_comp(EmstArgs a) {
@@ -850,7 +859,7 @@ hipError_t launch_em_search(const EmstArgs& a, const int32_t* list, int64_t coun
 
 hipError_t launch_em_merge_edges(const EmstArgs& a, hipStream_t s) {
     k_em_cmin<<<em_blocks(a.n, 256), 256, 0, s>>>(a);
-    k_em_hook<<<em_blocks(a.n, kEmPass), kEmPass, 0, s>>>(a);
+    k_em_hook<<<em_blocks(a.roots ? a.nroots : a.n, kEmPass), kEmPass, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -880,7 +889,7 @@ hipError_t launch_em_search_grid(const EmstArgs& a, int64_t active, hipStream_t 
 }
 
 hipError_t launch_em_jump(const EmstArgs& a, int src, hipStream_t s) {
-    k_em_jump<<<em_blocks(a.n, 256), 256, 0, s>>>(a, src);
+    k_em_jump<<<em_blocks(a.roots ? a.nroots : a.n, 256), 256, 0, s>>>(a, src);
     return hipGetLastError();
 }
 

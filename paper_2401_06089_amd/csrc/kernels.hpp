@@ -283,6 +283,9 @@ struct EmstArgs {
     uint64_t* cmin_w;          // [n] per component root: least mrd2 (bits)
     uint64_t* cmin_e;          // [n] per component root: least (lo << 32 | hi) input indices at that weight
     int32_t* parent[2];        // [n] hooking and pointer jumping
+    const int32_t* roots;      // [nroots] this round's component roots (null: every point)
+    int64_t nroots;
+    int32_t* roots_next;       // [n] the next round's roots, appended by the relabelling
     uint64_t* ew;              // [n-1] tree edges as recorded: mrd2 bits, endpoints
     int32_t* ea;
     int32_t* eb;

@@ -1024,7 +1024,7 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
 
 struct EmstLayout {
     size_t core2, comp, comp2, best_w, best_j, active, cmin_w, cmin_e, par0, par1, ew, ea, eb, counters, pairs, bbox,
-        sctrl, skey[2], sval[2], slb[2],
+        sctrl, skey[2], sval[2], slb[2], roots[2],
         cellof, cstart, cfill, sorted, slotof, spts, partial, fallback, scan_agg;
     int64_t len = 0;        // edge-list length (n - 1, at least 1)
     int64_t slb_words = 0;  // look-back words of one radix pass
@@ -1057,6 +1057,8 @@ EmstLayout make_emst_layout(int64_t n) {
     E.eb = take(c, 4 * E.len);
     E.counters = take(c, 32);
     E.pairs = take(c, 8 * kEmstPairSlots);
+    E.roots[0] = take(c, 4 * n);
+    E.roots[1] = take(c, 4 * n);
     E.sctrl = take(c, sizeof(Control));
     for (int k = 0; k < 2; ++k) {
         E.skey[k] = take(c, 4 * E.len);
@@ -1233,6 +1235,12 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
         PD_TIMED(PK_EM_CORE, pair_ops, launch_em_core(a, nullptr, 0, s));
     }
     int64_t comps = n;
+    // component roots: every point in the first round, then the list the
+    // relabelling appends (two buffers in turn)
+    int32_t* RL[2] = {at<int32_t>(d, E.roots[0]), at<int32_t>(d, E.roots[1])};
+    int rcur = -1;
+    a.roots = nullptr;
+    a.nroots = n;
     for (int round = 0; comps > 1; ++round) {
         if (round > 64) return PANDORA_ERR_HIP;           // every round at least halves the components
         PD_TRY(launch_clear_words(a.counters + 3, 2, s));
@@ -1268,12 +1276,16 @@ int run_emst(int64_t n, int32_t dim, const float* points, int32_t min_pts, int32
             if (hc[3] == 0) break;
         }
         PD_TRY(launch_clear_words(a.counters + 1, 1, s));
+        a.roots_next = RL[rcur == 0 ? 1 : 0];
         PD_TIMED(PK_EM_MERGE, 40.0 * (double)n, launch_em_relabel(a, src, s));
         rc2 = read_counters();
         if (rc2 != PANDORA_OK) return rc2;
         if (hc[2]) return PANDORA_ERR_HIP;
         if ((int64_t)hc[1] >= comps) return PANDORA_ERR_HIP;   // no progress: cannot happen
         comps = hc[1];
+        rcur = rcur == 0 ? 1 : 0;
+        a.roots = RL[rcur];
+        a.nroots = comps;
     }
     if ((int64_t)hc[0] != n - 1) return PANDORA_ERR_HIP;
 
