@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark: single-linkage dendrograms of MSTs on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--steps K] [--warmup W] [--workload c3]
 
 A step is one pass of the whole method (weight sort, contraction levels,
 expansion, chain sort, stitch) over one batch of synthetic input that is
-already resident in HBM.  The default workload is the two 10,000,000-vertex
-single trees (a random recursive tree with fp32 uniform weights and a
-caterpillar with a rising spine), one call per tree; a step builds both.
+already resident in HBM.  The default workload is the largest single tree:
+a preferential-attachment tree of 50,000,000 vertices with lognormal fp32
+weights and 5 % ten-fold bridges, one call per step.
 
 Printed: one JSON line with the throughput (MST edges per second), the
 roofline of the dominant kernel (algorithmic bytes per launch over its mean
-HIP-event duration on the library's stream, against 8 TB/s), and the CPU
-oracle timed on this host on the same inputs.
+HIP-event duration on the library's stream, against 8 TB/s), the CPU oracle
+timed on this host on the same inputs (its comparison sort on every host
+thread and on one, each timed apart from the sequential union-find sweep),
+and, for the default workload, two short side measurements: the 4,096-tree
+forest in one batched call against one call per tree, and a short serving
+run.
 """
 from __future__ import annotations
 
@@ -149,7 +153,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-extras", action="store_true",
+                    help="c3: skip the side measurements (batched forest, short serving run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="capture each call once into a HIP graph and replay it every step")
@@ -397,55 +403,148 @@ def main():
             flat_baseline(out)
         print(json.dumps(out), flush=True)
         return
+    if not args.no_extras and args.workload == "c3":
+        out["c4_batched"] = side_batched(dev)
+        out["c5_serving_short"] = side_serving(dev)
     if not args.no_cpu_baseline:
-        import oracle
-        log("timing the CPU oracle on the same inputs ...")
+        oracle_baseline(out, items, args.workload)
+    print(json.dumps(out), flush=True)
+
+
+def host_threads() -> int:
+    """Host threads this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set (the share of the host given to one GPU)."""
+    try:
+        t = len(os.sched_getaffinity(0))
+    except AttributeError:
+        t = os.cpu_count() or 1
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return min(t, omp) if omp > 0 else t
+
+
+def oracle_baseline(out, items, workload):
+    """The CPU oracle on the step's own inputs, on this host: its (w, id)
+    comparison sort on every host thread and on one, each timed apart from
+    the sequential union-find sweep (the shape of the paper's multithreaded
+    union-find comparison: a parallel sort, then a sequential sweep)."""
+    import numpy as np
+    import oracle
+    threads = host_threads()
+    total_edges = sum(obj.m if kind == "tree" else obj.m_total for kind, obj in items)
+    runs = {}
+    results = []
+    for T in (threads, 1):
+        log(f"timing the CPU oracle on the same inputs, {T} thread(s) ...")
+        sort_s = sweep_s = 0.0
         t1 = time.perf_counter()
-        results = []
+        res = []
         for kind, obj in items:
             if kind == "tree":
-                results.append(oracle.dendrogram(obj.n, obj.u, obj.v, obj.w))
+                ep, vp, a, b = oracle.dendrogram_timed(obj.n, obj.u, obj.v, obj.w, threads=T)
+                sort_s += a
+                sweep_s += b
+                res.append((ep, vp))
             else:
-                results.append(oracle.dendrogram_batched(obj.voff, obj.u, obj.v, obj.w))
-        cpu_s = time.perf_counter() - t1
-        # Imbalance (the paper's Table 2): dendrogram height over log2 n, from
-        # the oracle's output; for a forest, the largest over its trees.
-        imb = []
-        for (kind, obj), (ep, vp) in zip(items, results):
-            if kind == "tree":
-                h = oracle.dendrogram_height(ep, vp)
-                imb.append({"n": obj.n, "height": h, "imb": h / math.log2(obj.n)})
-            else:
-                worst = None
-                for b in range(obj.B):
-                    v0, v1 = int(obj.voff[b]), int(obj.voff[b + 1])
-                    if v1 - v0 < 2:
-                        continue
-                    h = oracle.dendrogram_height(ep[v0 - b:v1 - b - 1], vp[v0:v1])
-                    r = h / math.log2(v1 - v0)
-                    if worst is None or r > worst["imb"]:
-                        worst = {"n": v1 - v0, "height": h, "imb": r, "tree": b}
-                imb.append(worst)
+                for bb in range(obj.B):
+                    v0, v1 = int(obj.voff[bb]), int(obj.voff[bb + 1])
+                    e0, e1 = v0 - bb, v1 - bb - 1
+                    ep, vp, a, b = oracle.dendrogram_timed(v1 - v0, obj.u[e0:e1], obj.v[e0:e1], obj.w[e0:e1],
+                                                           threads=T)
+                    sort_s += a
+                    sweep_s += b
+                res.append(None)
+        wall = time.perf_counter() - t1
+        runs[T] = {"value": total_edges / wall, "seconds": wall, "sort_s": sort_s, "sweep_s": sweep_s}
+        if T == 1:
+            results = res
+    # Imbalance (the paper's Table 2): dendrogram height over log2 n, from
+    # the oracle's output (single trees).
+    imb = []
+    for (kind, obj), r in zip(items, results):
+        if kind == "tree" and r is not None:
+            h = oracle.dendrogram_height(r[0], r[1])
+            imb.append({"n": obj.n, "height": h, "imb": h / math.log2(obj.n)})
+    if imb:
         out["config"]["imbalance"] = imb
-        # The multithreaded CPU form of the same method (single trees only),
-        # checked against the oracle's output on the same inputs.
-        if all(kind == "tree" for kind, _ in items):
-            from paper_2401_06089_amd import cpu as pcpu
-            threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-            t2 = time.perf_counter()
-            mt = [pcpu.dendrogram(obj.n, obj.u, obj.v, obj.w, threads=threads) for _, obj in items]
-            mt_s = time.perf_counter() - t2
-            ok = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(mt, results))
-            out["cpu_pandora_mt"] = {"value": total_edges / mt_s, "unit": "edges/s", "threads": threads,
-                                     "seconds": mt_s, "matches_oracle": ok,
-                                     "speedup_vs_oracle": cpu_s / mt_s}
-        out["cpu_baseline"] = {"value": total_edges / cpu_s, "unit": "edges/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"one full step of {args.workload} ({total_edges} edges), "
-                                         f"single-threaded sort + union-find sweep",
-                               "seconds": cpu_s, "host_cpu": cpu_model(),
-                               "host_threads_available": os.cpu_count()}
-    print(json.dumps(out), flush=True)
+    # The multithreaded CPU form of the same method (single trees only),
+    # checked against the oracle's output on the same inputs.
+    if all(kind == "tree" for kind, _ in items):
+        from paper_2401_06089_amd import cpu as pcpu
+        t2 = time.perf_counter()
+        mt = [pcpu.dendrogram(obj.n, obj.u, obj.v, obj.w, threads=threads) for _, obj in items]
+        mt_s = time.perf_counter() - t2
+        ok = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(mt, results))
+        out["cpu_pandora_mt"] = {"value": total_edges / mt_s, "unit": "edges/s", "threads": threads,
+                                 "seconds": mt_s, "matches_oracle": ok,
+                                 "speedup_vs_oracle": runs[threads]["seconds"] / mt_s}
+    par, one = runs[threads], runs[1]
+    out["cpu_baseline"] = {
+        "value": par["value"], "unit": "edges/s", "cores": threads, "kind": "oracle",
+        "sample": f"one full step of {workload} ({total_edges} edges): comparison merge sort of (w, id) on "
+                  f"{threads} host threads, then the sequential union-find sweep",
+        "seconds": par["seconds"], "sort_s": par["sort_s"], "sweep_s": par["sweep_s"],
+        "single_thread": {"value": one["value"], "seconds": one["seconds"], "sort_s": one["sort_s"],
+                          "sweep_s": one["sweep_s"]},
+        "host_cpu": cpu_model(), "host_threads_available": os.cpu_count(),
+        "gpu_speedup_vs_oracle": out["value"] / par["value"],
+    }
+
+
+def side_batched(dev, reps=5):
+    """The 4,096-tree forest (about 5e7 edges) in one batched call, against
+    the same trees built one call per tree on the same stream."""
+    import torch
+    import gen
+    import paper_2401_06089_amd as pd
+    f = gen.c4_batched(0)
+    u = torch.from_numpy(f.u).to(dev)
+    v = torch.from_numpy(f.v).to(dev)
+    w = torch.from_numpy(f.w).to(dev)
+    pd.dendrogram_batched(f.voff, u, v, w)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        pd.dendrogram_batched(f.voff, u, v, w)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - a)
+    batched = statistics.median(ts)
+    trees = []
+    for b in range(f.B):
+        v0, v1 = int(f.voff[b]), int(f.voff[b + 1])
+        e0, e1 = v0 - b, v1 - b - 1
+        trees.append((v1 - v0, u[e0:e1], v[e0:e1], w[e0:e1],
+                      torch.empty(max(e1 - e0, 0), dtype=torch.int32, device=dev),
+                      torch.empty(v1 - v0, dtype=torch.int32, device=dev)))
+
+    def per_tree():
+        for t in trees:
+            st = pd.dendrogram_into(*t)
+            if st != pd.OK:
+                raise RuntimeError(pd.status_string(st))
+    per_tree()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    per_tree()
+    torch.cuda.synchronize()
+    per_s = time.perf_counter() - a
+    del trees, u, v, w
+    torch.cuda.empty_cache()
+    return {"workload": "c4", "description": WORKLOADS["c4"], "trees": f.B, "edges": int(f.m_total),
+            "batched_ms": 1000 * batched, "batched_edges_per_s": f.m_total / batched,
+            "per_tree_calls_ms": 1000 * per_s, "per_tree_edges_per_s": f.m_total / per_s,
+            "batched_speedup": per_s / batched, "reps": reps}
+
+
+def side_serving(dev):
+    """A short open-loop serving run (the c5 mix at 2,000 requests/s) from a
+    smaller device pool."""
+    ns = argparse.Namespace(rate=2000.0, duration=15.0, discard=3.0, pool=96, streams=4, budget_gb=200.0,
+                            max_batch_edges=8_000_000, policy="small_first")
+    r = run_serving(ns, dev, emit=False)
+    return {"workload": "c5", "duration_s": ns.duration, "discarded_s": ns.discard, "pool_trees": ns.pool,
+            "rate_per_s": ns.rate, "edges_per_s": r["value"], "latency_ms": r["latency_ms"],
+            "requests": r["requests"]}
 
 
 def uniform_points(n, dim, seed):
@@ -539,7 +638,7 @@ def flat_baseline(out):
                            "host_threads_available": os.cpu_count()}
 
 
-def run_serving(args, dev):
+def run_serving(args, dev, emit=True):
     """Open-loop serving run: Poisson arrivals, continuous batching, p50/p99 latency."""
     import numpy as np
     import torch
@@ -635,7 +734,11 @@ def run_serving(args, dev):
                      "batches": srv.batches, "max_concurrent_batches": srv.max_concurrent,
                      "peak_admitted_bytes": srv.peak_in_use, "wall_s": end - start},
     }
-    print(json.dumps(out), flush=True)
+    del pool
+    torch.cuda.empty_cache()
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -39,7 +39,7 @@ _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 def build() -> str:
     """Compile oracle.c into liboracle.so next to it (plain gcc)."""
     tmp = _LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-pthread", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -60,6 +60,12 @@ def _load():
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p]
     lib.oracle_dendrogram_batched.restype = ctypes.c_int
+    lib.oracle_dendrogram_mt.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.oracle_dendrogram_mt.restype = ctypes.c_int
+    lib.oracle_edge_order_mt.argtypes = [ctypes.c_int64, _f32p, _i32p, ctypes.c_int]
+    lib.oracle_edge_order_mt.restype = ctypes.c_int
     lib.oracle_dendrogram_height.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
     lib.oracle_dendrogram_height.restype = ctypes.c_int64
     _lib = lib
@@ -76,11 +82,11 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None and a.size else None
 
 
-def edge_order(w: np.ndarray) -> np.ndarray:
-    """Edge ids sorted ascending by (w, id)."""
+def edge_order(w: np.ndarray, threads: int = 1) -> np.ndarray:
+    """Edge ids sorted ascending by (w, id) (a merge sort on `threads` host threads)."""
     w = np.ascontiguousarray(w, dtype=np.float32)
     out = np.empty(len(w), np.int32)
-    st = _load().oracle_edge_order(len(w), w, out)
+    st = _load().oracle_edge_order_mt(len(w), w, out, int(threads))
     if st:
         raise OracleError(st)
     return out
@@ -104,6 +110,24 @@ def dendrogram(n, u, v, w):
     if st:
         raise OracleError(st)
     return ep, vp
+
+
+def dendrogram_timed(n, u, v, w, threads: int = 1):
+    """(edge_parent, vertex_parent, sort_seconds, sweep_seconds) of one tree:
+    the (w, id) sort on `threads` host threads, then the sequential union-find
+    sweep, each timed inside the C code."""
+    u = np.ascontiguousarray(u, dtype=np.int32)
+    v = np.ascontiguousarray(v, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    ep = np.empty(max(n - 1, 0), np.int32)
+    vp = np.empty(max(n, 0), np.int32)
+    ts, tw = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    st = _load().oracle_dendrogram_mt(int(n), _ptr(u), _ptr(v), _ptr(w), _ptr(ep),
+                                      vp.ctypes.data_as(ctypes.c_void_p) if vp.size else None, int(threads),
+                                      ctypes.byref(ts), ctypes.byref(tw))
+    if st:
+        raise OracleError(st)
+    return ep, vp, ts.value, tw.value
 
 
 def dendrogram_batched(voff, u, v, w):

@@ -33,10 +33,13 @@
  *   0 ok, 1 invalid argument, 2 not a tree, 3 NaN weight, 6 vertex id out of
  *   range.  Checks run in the order: arguments, vertex ids, NaN, tree.
  */
+#define _POSIX_C_SOURCE 200809L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <pthread.h>
+#include <time.h>
 
 enum {
     ORC_OK = 0,
@@ -74,10 +77,107 @@ static int32_t orc_find(int32_t* parent, int32_t x)
 }
 
 /*
- * Sort edge ids 0..m-1 by (w, id) ascending into order[].  Returns a status.
- * Exposed on its own so tests can check the ordering step by itself.
+ * Sorting by (w, id) on T host threads: the keys are cut into T runs, each run
+ * is sorted by qsort with the comparator above on its own thread, and sorted
+ * runs are merged pairwise, each merge of a round on its own thread, until
+ * one run is left.  Every edge id is distinct, so the order is total and the
+ * result does not depend on T.  (A comparison sort; it shares nothing with the
+ * GPU's radix passes.)
  */
-int oracle_edge_order(int64_t m, const float* w, int32_t* order)
+typedef struct {
+    orc_edge_key* src;
+    orc_edge_key* dst;
+    int64_t lo, mid, hi;   /* sort: [lo, hi); merge: [lo, mid) with [mid, hi) */
+} orc_job;
+
+static void* orc_sort_run(void* p)
+{
+    orc_job* j = (orc_job*)p;
+    qsort(j->src + j->lo, (size_t)(j->hi - j->lo), sizeof(orc_edge_key), orc_cmp);
+    return NULL;
+}
+
+static void* orc_merge_runs(void* p)
+{
+    orc_job* j = (orc_job*)p;
+    int64_t a = j->lo, b = j->mid, o = j->lo;
+    while (a < j->mid && b < j->hi) {
+        /* take the right run's key only when it is strictly lighter */
+        if (orc_cmp(&j->src[b], &j->src[a]) < 0) j->dst[o++] = j->src[b++];
+        else j->dst[o++] = j->src[a++];
+    }
+    while (a < j->mid) j->dst[o++] = j->src[a++];
+    while (b < j->hi) j->dst[o++] = j->src[b++];
+    return NULL;
+}
+
+/* Runs fn over jobs[0..k) on k threads (the calling thread takes the last). */
+static int orc_run_jobs(void* (*fn)(void*), orc_job* jobs, int k)
+{
+    pthread_t tid[256];
+    int started = 0, rc = 0;
+    for (int i = 0; i + 1 < k; ++i) {
+        if (pthread_create(&tid[i], NULL, fn, &jobs[i]) != 0) { rc = -1; break; }
+        ++started;
+    }
+    for (int i = started; i < k; ++i) fn(&jobs[i]);   /* what did not get a thread runs here */
+    for (int i = 0; i < started; ++i) pthread_join(tid[i], NULL);
+    return rc;
+}
+
+/* keys[0..m) sorted in place by (w, id) on `threads` threads. */
+static int orc_sort_keys(orc_edge_key* keys, int64_t m, int threads)
+{
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    if ((int64_t)threads > m / 4096 + 1) threads = (int)(m / 4096 + 1);   /* tiny inputs: one run */
+    if (threads == 1) {
+        qsort(keys, (size_t)m, sizeof(orc_edge_key), orc_cmp);
+        return ORC_OK;
+    }
+    orc_edge_key* tmp = (orc_edge_key*)malloc((size_t)m * sizeof(orc_edge_key));
+    if (!tmp) return ORC_INVALID_ARG;
+    int64_t bound[257];
+    for (int t = 0; t <= threads; ++t) bound[t] = m * t / threads;
+    orc_job jobs[256];
+    for (int t = 0; t < threads; ++t) {
+        jobs[t].src = keys;
+        jobs[t].dst = NULL;
+        jobs[t].lo = bound[t];
+        jobs[t].mid = bound[t];
+        jobs[t].hi = bound[t + 1];
+    }
+    orc_run_jobs(orc_sort_run, jobs, threads);
+    orc_edge_key* src = keys;
+    orc_edge_key* dst = tmp;
+    for (int width = 1; width < threads; width *= 2) {
+        int k = 0;
+        for (int t = 0; t < threads; t += 2 * width) {
+            const int tm = t + width < threads ? t + width : threads;
+            const int th = t + 2 * width < threads ? t + 2 * width : threads;
+            jobs[k].src = src;
+            jobs[k].dst = dst;
+            jobs[k].lo = bound[t];
+            jobs[k].mid = bound[tm];
+            jobs[k].hi = bound[th];
+            ++k;
+        }
+        orc_run_jobs(orc_merge_runs, jobs, k);
+        orc_edge_key* x = src;
+        src = dst;
+        dst = x;
+    }
+    if (src != keys) memcpy(keys, src, (size_t)m * sizeof(orc_edge_key));
+    free(tmp);
+    return ORC_OK;
+}
+
+/*
+ * Sort edge ids 0..m-1 by (w, id) ascending into order[], on `threads` host
+ * threads.  Returns a status.  Exposed on its own so tests can check the
+ * ordering step by itself.
+ */
+int oracle_edge_order_mt(int64_t m, const float* w, int32_t* order, int threads)
 {
     if (m < 0 || (m > 0 && (!w || !order))) return ORC_INVALID_ARG;
     orc_edge_key* keys = (orc_edge_key*)malloc((size_t)(m > 0 ? m : 1) * sizeof(orc_edge_key));
@@ -87,20 +187,36 @@ int oracle_edge_order(int64_t m, const float* w, int32_t* order)
         keys[i].w = w[i];
         keys[i].id = (int32_t)i;
     }
-    qsort(keys, (size_t)m, sizeof(orc_edge_key), orc_cmp);
-    for (int64_t i = 0; i < m; ++i) order[i] = keys[i].id;
+    const int st = orc_sort_keys(keys, m, threads);
+    if (st == ORC_OK)
+        for (int64_t i = 0; i < m; ++i) order[i] = keys[i].id;
     free(keys);
-    return ORC_OK;
+    return st;
+}
+
+int oracle_edge_order(int64_t m, const float* w, int32_t* order)
+{
+    return oracle_edge_order_mt(m, w, order, 1);
+}
+
+static double orc_now(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
 
 /*
  * Dendrogram of one tree with n vertices and n-1 edges; edge i joins u[i] and
  * v[i] with weight w[i].  Writes edge_parent[n-1] and vertex_parent[n] (input
  * edge ids, -1 for "no parent").  All pointers are host pointers owned by the
- * caller.
+ * caller.  The sort runs on `threads` host threads; the union-find sweep is
+ * sequential.  When given, *sort_seconds and *sweep_seconds receive the wall
+ * time of the two phases.
  */
-int oracle_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const float* w,
-                      int32_t* edge_parent, int32_t* vertex_parent)
+int oracle_dendrogram_mt(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                         int32_t* edge_parent, int32_t* vertex_parent, int threads,
+                         double* sort_seconds, double* sweep_seconds)
 {
     if (n < 1 || n > INT32_MAX) return ORC_INVALID_ARG;
     const int64_t m = n - 1;
@@ -119,7 +235,10 @@ int oracle_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const float
         return ORC_INVALID_ARG;
     }
 
-    int status = oracle_edge_order(m, w, order);
+    const double t0 = orc_now();
+    int status = oracle_edge_order_mt(m, w, order, threads);
+    const double t1 = orc_now();
+    if (sort_seconds) *sort_seconds = t1 - t0;
     if (status != ORC_OK) goto done;
 
     for (int64_t x = 0; x < n; ++x) {
@@ -150,10 +269,17 @@ int oracle_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const float
         top[r] = e;
     }
     /* The heaviest edge is the root and keeps edge_parent == -1. */
+    if (sweep_seconds) *sweep_seconds = orc_now() - t1;
 
 done:
     free(order); free(parent); free(size); free(top);
     return status;
+}
+
+int oracle_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                      int32_t* edge_parent, int32_t* vertex_parent)
+{
+    return oracle_dendrogram_mt(n, u, v, w, edge_parent, vertex_parent, 1, NULL, NULL);
 }
 
 /*

@@ -30,6 +30,33 @@ def test_edge_order_matches_lexsort():
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("threads", [2, 3, 8, 16])
+@pytest.mark.parametrize("m", [0, 1, 4097, 50_000, 300_001])
+def test_threaded_edge_order_matches_lexsort(m, threads):
+    # the merge of sorted runs on several threads gives the same total order
+    rng = np.random.default_rng(m + threads)
+    w = (rng.integers(0, 40, m).astype(np.float32) - 20) * np.float32(0.25)   # many ties, both signs
+    if m > 4:
+        w[:4] = [-0.0, 0.0, np.inf, -np.inf]
+    want = np.lexsort((np.arange(m), w.astype(np.float64) + 0.0))
+    assert np.array_equal(oracle.edge_order(w, threads=threads), want)
+
+
+@pytest.mark.parametrize("threads", [1, 4])
+def test_timed_dendrogram_equals_plain_and_brute_force(threads):
+    for seed in range(6):
+        t = gen.shuffled(gen.rrt(30, seed), seed)
+        t.w[:] = np.random.default_rng(seed).integers(0, 4, 29).astype(np.float32)   # ties
+        ep, vp, ts, tw = oracle.dendrogram_timed(t.n, t.u, t.v, t.w, threads=threads)
+        bep, bvp = brute_force(t.n, t.u, t.v, t.w)
+        assert np.array_equal(ep, bep) and np.array_equal(vp, bvp)
+        assert ts >= 0.0 and tw >= 0.0
+    t = gen.c1_rrt(0)
+    ep, vp, _, _ = oracle.dendrogram_timed(t.n, t.u, t.v, t.w, threads=threads)
+    pep, pvp = oracle.dendrogram(t.n, t.u, t.v, t.w)
+    assert np.array_equal(ep, pep) and np.array_equal(vp, pvp)
+
+
 def test_signed_zero_ties_fall_to_id():
     w = np.array([0.0, -0.0, 0.0, -0.0], np.float32)
     assert list(oracle.edge_order(w)) == [0, 1, 2, 3]
