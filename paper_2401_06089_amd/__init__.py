@@ -267,9 +267,19 @@ def hdbscan(points: torch.Tensor, min_pts: int, min_cluster_size: int, stream=No
     """HDBSCAN* end to end on the GPU: the mutual-reachability MST, its
     dendrogram and the excess-of-mass flat clusters.  Returns (labels[n],
     stability[k]) as device tensors (labels numbered by smallest point index,
-    -1 = noise)."""
+    -1 = noise).
+
+    Clouds where min_pts or more points coincide are refused (INVALID_ARG):
+    their mutual-reachability distance is 0, where the density level
+    lambda = 1/w of the flat-cluster step is not finite."""
     u, v, _, w32 = emst(points, min_pts, stream=stream)
-    labels, stab, _, _ = flat_clusters(u, v, w32, min_cluster_size, n=points.shape[0], stream=stream)
+    try:
+        labels, stab, _, _ = flat_clusters(u, v, w32, min_cluster_size, n=points.shape[0], stream=stream)
+    except PandoraError as e:
+        if e.status == INVALID_ARG and int(min_cluster_size) >= 2:
+            raise PandoraError(INVALID_ARG, "min_pts or more points coincide (mutual-reachability distance 0, "
+                                            "lambda = 1/w not finite): flat clusters need every MST weight > 0") from e
+        raise
     return labels, stab
 
 

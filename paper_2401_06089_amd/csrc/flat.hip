@@ -353,7 +353,6 @@ __global__ void k_fc_clear(FlatArgs a) {
         a.ext[i] = 0;
         a.bigcnt[i] = 0;
         a.bigmax[i] = 0;
-        a.stab[i] = 0.0;
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.lb_words; i += stride) a.lb[0][i] = 0;
     if (blockIdx.x == 0 && threadIdx.x < 4) a.counters[threadIdx.x] = 0;   // births, errors, paths done, heads
@@ -376,31 +375,93 @@ __global__ void k_fc_prepare(FlatArgs a) {
     if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&a.counters[1], 1u);
 }
 
-// fp64 sum of val into base[key] for the lanes with act.  Lanes that share
-// the first active lane's key (edges of one large cluster, usually) send
-// one combined sum.  Every lane of the wave must call it.
-__device__ void wave_add_into(double* base, int32_t key, double val, bool act) {
+// Exact stabilities.  Every term is an fp64 value t = d * lambda (or the birth
+// term -size * lambda_birth) with lambda = 1/w for an fp32 weight w > 0, so
+// |t| lies in [2^-180, 2^180] and is an integer multiple of 2^-180.  Each
+// cluster therefore sums its terms exactly in a fixed-point accumulator of
+// kAccChunks signed 64-bit words, word k holding a multiple of
+// 2^(32k + kAccBase): a term adds its 53-bit significand, shifted into place,
+// as three 32-bit pieces.  At most n - 1 < 2^31 pieces below 2^32 meet in a
+// word, so no word overflows, and integer sums do not depend on their order.
+// The finished sum is rounded once to the nearest double (ties to even): the
+// correctly rounded sum of the terms, whatever the order of the additions.
+constexpr int kAccBase = -192;
+
+struct TermPieces {
+    int k;                  // first accumulator word
+    int64_t p0, p1, p2;     // signed pieces for words k, k+1, k+2
+};
+
+__device__ __forceinline__ TermPieces term_pieces(double t) {
+    TermPieces r{0, 0, 0, 0};
+    const uint64_t bits = (uint64_t)__double_as_longlong(t);
+    const int bexp = (int)((bits >> 52) & 0x7ff);
+    if (bexp == 0) return r;                        // zero (the range above has no subnormal terms)
+    const uint64_t mant = (bits & ((1ull << 52) - 1)) | (1ull << 52);
+    const int shift = (bexp - 1075) - kAccBase;     // t = mant * 2^(bexp - 1075)
+    const int k = shift >> 5, o = shift & 31;
+    const uint64_t lo = mant << o;                  // bits [0, 64) of mant * 2^o
+    const uint64_t hi = o ? (mant >> (64 - o)) : 0; // bits [64, 85)
+    r.k = k;
+    r.p0 = (int64_t)(lo & 0xffffffffull);
+    r.p1 = (int64_t)(lo >> 32);
+    r.p2 = (int64_t)hi;
+    if (bits >> 63) {
+        r.p0 = -r.p0;
+        r.p1 = -r.p1;
+        r.p2 = -r.p2;
+    }
+    return r;
+}
+
+// Adds the pieces of t into accumulator acc (kAccChunks words; pieces beyond
+// the last word cannot occur for terms in range).
+__device__ __forceinline__ void acc_add_term(unsigned long long* acc, double t) {
+    const TermPieces q = term_pieces(t);
+    if (q.p0) atomicAdd(acc + q.k, (unsigned long long)q.p0);
+    if (q.p1) atomicAdd(acc + q.k + 1, (unsigned long long)q.p1);
+    if (q.p2 && q.k + 2 < kAccChunks) atomicAdd(acc + q.k + 2, (unsigned long long)q.p2);
+}
+
+// Sums the terms of the lanes with act into cluster accumulators.  Lanes that
+// share the first active lane's cluster (edges of one large cluster, usually)
+// add their pieces word by word across the wave first (exact integer sums)
+// and send one atomic per word.  Every lane of the wave must call it.
+__device__ void wave_acc_into(unsigned long long* acc, int32_t ci, double t, bool act) {
     const uint64_t m = ballot(act);
     if (!m) return;
     const int leader = __ffsll((long long)m) - 1;
-    const int32_t k0 = __shfl(key, leader, kWave);
-    const bool same = act && key == k0;
-    double v = same ? val : 0.0;
+    const int32_t c0 = __shfl(ci, leader, kWave);
+    const bool same = act && ci == c0;
+    const TermPieces q = same ? term_pieces(t) : TermPieces{0, 0, 0, 0};
+    // the lanes' first words span a range [kmin, kmax]; combine word by word
+    int kmin = same ? q.k : kAccChunks, kmax = same ? q.k + 2 : -1;
 #pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    if (lane_id() == leader) unsafeAtomicAdd(&base[k0], v);
-    if (act && !same) unsafeAtomicAdd(&base[key], val);
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        kmin = min(kmin, __shfl_xor(kmin, d, kWave));
+        kmax = max(kmax, __shfl_xor(kmax, d, kWave));
+    }
+    if (kmax >= kAccChunks) kmax = kAccChunks - 1;
+    for (int w = kmin; w <= kmax; ++w) {
+        int64_t x = (w == q.k ? q.p0 : 0) + (w == q.k + 1 ? q.p1 : 0) + (w == q.k + 2 ? q.p2 : 0);
+        if (!same) x = 0;
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+        if (lane_id() == leader && x != 0) atomicAdd(acc + (int64_t)c0 * kAccChunks + w, (unsigned long long)x);
+    }
+    if (act && !same) acc_add_term(acc + (int64_t)ci * kAccChunks, t);
 }
 
 // Departure terms count * lambda per edge node of a cluster region, the birth
-// term -size * lambda_birth, and each born cluster's parent cluster.
+// term -size * lambda_birth, and each born cluster's parent cluster.  Born
+// clusters are already numbered (cidx), and their accumulators cleared.
 __global__ void k_fc_stab(FlatArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int32_t root = (int32_t)a.m;
     const int lane = lane_id();
     for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); e0 < a.m; e0 += stride) {
         const int64_t e = e0 + lane;
-        int32_t c = -1;
+        int32_t ci = -1;
         double term = 0.0;
         bool born = false;
         const int32_t sz = e < a.m ? a.size[e] : 0;
@@ -411,25 +472,91 @@ __global__ void k_fc_stab(FlatArgs a) {
             } else {
                 const int32_t d = a.bigcnt[e] == 1u ? sz - a.bigmax[e] : sz;
                 if (ce != root) {
-                    c = ce;
+                    ci = a.cidx[ce];
                     term = (double)d * (1.0 / (double)a.w[e]);
+                    if (ci < 0 || ci >= a.K) {               // not a numbered cluster
+                        atomicOr(&a.counters[1], 2u);
+                        ci = -1;
+                    }
                 }
-                if (ce == (int32_t)e) {
+                if (ce == (int32_t)e && ci >= 0) {
                     const int32_t p = a.ep[e];                // a born edge always has a parent
                     if (p < 0 || p >= a.m) {
                         atomicOr(&a.counters[1], 2u);
                     } else {
                         const double lamb = 1.0 / (double)a.w[p];
-                        unsafeAtomicAdd(&a.stab[e], -((double)sz * lamb));
+                        acc_add_term(a.acc + (int64_t)ci * kAccChunks, -((double)sz * lamb));
                         a.cpar[e] = a.T[p];
                         born = true;
                     }
                 }
             }
         }
-        wave_add_into(a.stab, c, term, c >= 0);
+        wave_acc_into(a.acc, ci, term, ci >= 0);
         const uint64_t b = ballot(born);
         if (b != 0 && lane == __ffsll((long long)b) - 1) atomicAdd(&a.counters[0], (uint32_t)popc64(b));
+    }
+}
+
+__global__ void k_fc_acc_clear(FlatArgs a) {
+    const int64_t K = *a.count < a.K ? *a.count : a.K;   // born clusters, counted by the birth scan
+    const int64_t words = K * kAccChunks;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) a.acc[i] = 0;
+}
+
+// The exact sum of cluster i, rounded to the nearest double (ties to even),
+// into stab[birth edge].
+__global__ void k_fc_acc_round(FlatArgs a) {
+    const int64_t K = *a.count < a.K ? *a.count : a.K;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += stride) {
+        const unsigned long long* w = a.acc + i * kAccChunks;
+        // carries: limbs of 32 bits, two's complement, with the sign in the top carry
+        uint32_t limb[kAccChunks];
+        int64_t carry = 0;
+        for (int k = 0; k < kAccChunks; ++k) {
+            const int64_t x = (int64_t)w[k] + carry;
+            limb[k] = (uint32_t)x;
+            carry = x >> 32;                          // arithmetic shift: floor division
+        }
+        const bool neg = carry < 0;
+        if (neg) {                                   // magnitude of the negative sum
+            uint64_t c = 1;
+            for (int k = 0; k < kAccChunks; ++k) {
+                const uint64_t x = (uint64_t)(uint32_t)~limb[k] + c;
+                limb[k] = (uint32_t)x;
+                c = x >> 32;
+            }
+        }
+        int top = kAccChunks - 1;
+        while (top >= 0 && limb[top] == 0) --top;
+        double val = 0.0;
+        if (top >= 0) {
+            const int hb = 32 * top + (31 - __clz((int)limb[top]));   // highest set bit of the magnitude
+            // the 53 bits from hb down, then the rounding bit and the sticky rest
+            auto bit = [&](int b) -> uint32_t { return b < 0 ? 0u : (limb[b >> 5] >> (b & 31)) & 1u; };
+            uint64_t mant = 0;
+            for (int b = hb; b > hb - 53; --b) mant = (mant << 1) | bit(b);
+            const int rb = hb - 53;
+            const uint32_t round = bit(rb);
+            bool sticky = false;                          // any bit below the rounding bit
+            if (rb > 0) {
+                const int lw = rb >> 5, lb = rb & 31;
+                sticky = lb != 0 && (limb[lw] & ((1u << lb) - 1u)) != 0;
+                for (int k = 0; k < lw && !sticky; ++k) sticky = limb[k] != 0;
+            }
+            int e2 = hb - 52 + kAccBase;                 // value = mant * 2^e2
+            if (round && (sticky || (mant & 1))) {
+                ++mant;
+                if (mant >> 53) {
+                    mant >>= 1;
+                    ++e2;
+                }
+            }
+            val = ldexp((double)mant, e2);
+        }
+        a.stab[a.clist[i]] = neg ? -val : val;
     }
 }
 
@@ -725,9 +852,14 @@ hipError_t launch_fc_clusters(const FlatArgs& a, int64_t lo, int64_t hi, hipStre
 }
 
 hipError_t launch_fc_stab(const FlatArgs& a, hipStream_t s) {
-    k_fc_stab<<<grid_for(a.m), 256, 0, s>>>(a);
+    // number the born clusters first: each owns one exact accumulator
     BirthScan p{a.T, a.clist, a.cidx, a.count, a.m};
-    return run_scan<OpSum>(p, a, s);
+    hipError_t e = run_scan<OpSum>(p, a, s);
+    if (e != hipSuccess) return e;
+    k_fc_acc_clear<<<grid_for(a.K * kAccChunks), 256, 0, s>>>(a);
+    k_fc_stab<<<grid_for(a.m), 256, 0, s>>>(a);
+    k_fc_acc_round<<<grid_for(a.K), 256, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_fc_tree(FlatArgs& a, int rounds, hipStream_t s) {

@@ -206,6 +206,7 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t s);
 // where it is born, the root cluster by m); the cluster tree then works on
 // dense indices 0..K-1 of the born clusters (K for the root).
 constexpr int kFcBlock = 1024;   // threads of a scan workgroup (4 elements each)
+constexpr int kAccChunks = 14;   // 64-bit words of one cluster's exact stability accumulator
 struct FlatArgs {
     int64_t n, m;
     int32_t mcs;               // minimum cluster size (>= 2)
@@ -221,10 +222,11 @@ struct FlatArgs {
     int32_t* bigmax;           // the largest such child
     int32_t* T;                // cluster of each edge node (birth edge id, or m)
     int32_t* cpar;             // parent cluster (edge id or m) of each born cluster
-    double* stab;              // stability of each born cluster
+    double* stab;              // stability of each born cluster (written once its sum is exact)
+    unsigned long long* acc;   // [K_max * kAccChunks] exact fixed-point stability sums (dense clusters)
     int32_t* cidx;             // dense index of each born cluster
     // per cluster, dense
-    int64_t K;                 // born clusters (set by the host once counted)
+    int64_t K;                 // born clusters: an upper bound before they are counted, then the count
     int32_t* clist;            // [K] birth edge of each cluster
     int32_t* cparD;            // [K] parent cluster, -1 = the root
     uint64_t* heavy;           // [K] (size << 32 | index) of the child with more vertices

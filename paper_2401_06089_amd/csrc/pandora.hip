@@ -807,7 +807,7 @@ int run_async(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v
 // ---- HDBSCAN* flat clusters ------------------------------------------------------
 
 struct FlatLayout {
-    size_t ext, size, bigcnt, bigmax, T, cpar, stab, cidx, clist, cparD, heavy, up0, up1, dist0, dist1, plen,
+    size_t ext, size, bigcnt, bigmax, T, cpar, stab, acc, cidx, clist, cparD, heavy, up0, up1, dist0, dist1, plen,
         poff, posof, lay, s_lay, b_lay, pending, ready, sel, jp0, jp1, tp0, tp1, minv, cnum, lb0, lb1, scan_ctr,
         keys, pos, count, counters;
     int64_t lb_words = 0;
@@ -829,6 +829,7 @@ FlatLayout make_flat_layout(int64_t N, int32_t mcs) {
     F.T = take(c, 4 * M);
     F.cpar = take(c, 4 * M);
     F.stab = take(c, 8 * M);
+    F.acc = take(c, 8 * kAccChunks * K);
     F.cidx = take(c, 4 * M);
     F.clist = take(c, 4 * K);
     F.cparD = take(c, 4 * K);
@@ -928,6 +929,8 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
     a.T = at<int32_t>(fb, FL.T);
     a.cpar = at<int32_t>(fb, FL.cpar);
     a.stab = at<double>(fb, FL.stab);
+    a.acc = at<unsigned long long>(fb, FL.acc);
+    a.K = std::min<int64_t>(M, 2 * (N / std::max<int32_t>(mcs, 2)) + 2);   // bound until counted
     a.cidx = at<int32_t>(fb, FL.cidx);
     a.clist = at<int32_t>(fb, FL.clist);
     a.cparD = at<int32_t>(fb, FL.cparD);

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 from oracle.emst import emst as oracle_emst
-from oracle.flat_clusters import decisions_safe, flat_clusters as oracle_flat
+from oracle.flat_clusters import flat_clusters as oracle_flat
 
 pytestmark = pytest.mark.gpu
 
@@ -91,10 +91,26 @@ def test_hdbscan_end_to_end(seed, min_pts, mcs):
     x = cloud(4000, 2 + seed % 2, seed, "blobs")
     lab, st = pd.hdbscan(torch.from_numpy(x).cuda(), min_pts, mcs)
     ou, ov, _, ow32, _ = oracle_emst(x, min_pts)
-    olab, ost, info = oracle_flat(len(x), ou, ov, ow32, mcs, return_info=True)
-    assert decisions_safe(info)
+    olab, ost = oracle_flat(len(x), ou, ov, ow32, mcs)
     assert np.array_equal(lab.cpu().numpy(), olab)
     assert st.numel() == ost.size >= 2
+    assert np.array_equal(st.cpu().numpy().view(np.uint64), ost.view(np.uint64))
+
+
+def test_hdbscan_rejects_coincident_points():
+    """min_pts or more coincident points are at mutual-reachability distance
+    0, where lambda = 1/w is not finite: hdbscan() refuses such clouds with
+    INVALID_ARG and says why (the MST itself is still available)."""
+    import paper_2401_06089_amd as pd
+    same = np.zeros((50, 2), np.float32)
+    x = np.concatenate([same, cloud(400, 2, 5, "normal")])
+    u, v, w64, w32 = pd.emst(torch.from_numpy(x).cuda(), 3)
+    assert (w32.cpu().numpy() == 0).sum() >= 49
+    with pytest.raises(pd.PandoraError) as ei:
+        pd.hdbscan(torch.from_numpy(x).cuda(), 3, 10)
+    assert ei.value.status == pd.INVALID_ARG and "coincide" in str(ei.value)
+    lab, st = pd.hdbscan(torch.from_numpy(cloud(400, 2, 5, "normal")).cuda(), 3, 10)   # a clean cloud still works
+    assert lab.numel() == 400
 
 
 def _exact_d2(x64, i, j):
