@@ -383,6 +383,9 @@ __global__ void k_fc_prepare(FlatArgs a) {
 // 2^(32k + kAccBase): a term adds its 53-bit significand, shifted into place,
 // as three 32-bit pieces.  At most n - 1 < 2^31 pieces below 2^32 meet in a
 // word, so no word overflows, and integer sums do not depend on their order.
+// A sum of fewer than 2^31 terms is below 2^211 in magnitude, so the 13 words
+// (bits 2^-192 .. 2^224) hold it, and the carry out of the top word is its
+// sign.
 // The finished sum is rounded once to the nearest double (ties to even): the
 // correctly rounded sum of the terms, whatever the order of the additions.
 constexpr int kAccBase = -192;

@@ -206,7 +206,7 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t s);
 // where it is born, the root cluster by m); the cluster tree then works on
 // dense indices 0..K-1 of the born clusters (K for the root).
 constexpr int kFcBlock = 1024;   // threads of a scan workgroup (4 elements each)
-constexpr int kAccChunks = 14;   // 64-bit words of one cluster's exact stability accumulator
+constexpr int kAccChunks = 13;   // 64-bit words of one cluster's exact stability accumulator
 struct FlatArgs {
     int64_t n, m;
     int32_t mcs;               // minimum cluster size (>= 2)
