@@ -103,7 +103,8 @@ __global__ void k_finalize(const Control* c, int32_t B, uint32_t* sticky) {
 }
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t value) {
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = value;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = value;
 }
 
 // The forest index: the tree of every 64th edge and vertex, closed by B-1.
@@ -147,7 +148,10 @@ hipError_t launch_finalize(const Control* c, int32_t B, uint32_t* sticky, hipStr
 }
 
 hipError_t launch_clear_words(uint32_t* p, int64_t n, hipStream_t s) {
-    k_fill_u32<<<1, 256, 0, s>>>(p, n, 0u);
+    if (n < 1) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_fill_u32<<<(unsigned)blocks, 256, 0, s>>>(p, n, 0u);
     return hipGetLastError();
 }
 
