@@ -25,10 +25,15 @@
  * pandora_workspace_bytes / pandora_release_workspaces).
  *
  * Execution: work is enqueued on `hip_stream` (NULL = the default stream).
- * The call returns when the dendrogram is complete: contraction reads one
- * small counter block back per large level, so the host waits for the
- * stream.  Calls on different streams may run concurrently from different
- * host threads; calls on the same stream are serialized.
+ * The plain calls (pandora_dendrogram, pandora_dendrogram_batched) return
+ * when the dendrogram is complete: contraction reads one small counter block
+ * back per large level, so the host waits for the stream, and every status,
+ * input errors included, comes back from the call.  This blocking form is
+ * the fastest for large trees (exact grids per level).  The stream-ordered
+ * form that never waits and defers input errors to pandora_stream_status is
+ * pandora_dendrogram_async / pandora_dendrogram_batched_async.  Calls on
+ * different streams may run concurrently from different host threads; calls
+ * on the same stream are serialized.
  *
  * Errors: the return value is a pandora_status_t.  Argument errors are
  * detected before any work is enqueued.  Input errors (ids out of range, NaN
@@ -159,8 +164,9 @@ PANDORA_API size_t pandora_workspace_bytes(int64_t n_total_vertices, int32_t B);
  *   labels[n]     chosen cluster of each vertex, numbered 0..k-1 in order of
  *                 each cluster's smallest vertex id; -1 = noise
  *   stability     NULL, or room for n / min_cluster_size doubles: the
- *                 stability of cluster i at index i (fp64 sums whose order of
- *                 additions is unspecified, so last bits may vary by run)
+ *                 stability of cluster i at index i: the correctly rounded
+ *                 sum of its fp64 terms (exact accumulation, rounded once),
+ *                 so the same on every run
  *   num_clusters  host pointer receiving k (may be NULL)
  * min_cluster_size >= 2.  Synchronous: returns after the stream has
  * finished the call.  Errors: INVALID_ARG (also for a weight <= 0 or NaN),

@@ -21,9 +21,10 @@
 // The size scan also counts, at each parent, the children with >= mcs
 // vertices.
 //
-// Stabilities are fp64 sums of count * lambda terms (lambda = 1 / w),
-// accumulated with atomics, so the order of additions (and the last bits)
-// vary; the selection compares them in fp64.
+// Stabilities are sums of fp64 count * lambda terms (lambda = 1 / w), each
+// accumulated exactly in fixed point and rounded once, so they are the
+// correctly rounded sums whatever order the atomics land in; the selection
+// compares them in fp64.
 //
 // Excess of mass runs on the cluster tree (each cluster splits into exactly
 // two or ends), whose depth reaches tens of thousands on skewed trees.  It is
