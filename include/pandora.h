@@ -118,6 +118,29 @@ PANDORA_API int pandora_dendrogram_batched_async(int32_t B, const int64_t* voff,
                                                  int32_t* vertex_parent, void* hip_stream);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results, errors and blocking behaviour as pandora_dendrogram,
+ * but the call makes no hipMalloc, hipFree or pinned host allocation: all of
+ * its scratch lives in one fixed device array of
+ * PANDORA_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs
+ * on until the process ends.
+ *   - Trees with pandora_workspace_bytes(n, 1) > PANDORA_NOALLOC_SCRATCH_BYTES
+ *     (more than PANDORA_NOALLOC_MAX_VERTICES vertices) return
+ *     PANDORA_ERR_OUT_OF_MEMORY before any work is enqueued.
+ *   - Every call on one GPU uses the same array, which keeps the last call's
+ *     contents (each call clears what it needs cleared).  Overlapping calls
+ *     would race on it, so the library holds a per-GPU lock from the start of
+ *     a call until its stream has finished it: calls from several threads run
+ *     one after the other.
+ *   - No profiler events are recorded; pandora_last_stats is kept.
+ */
+#define PANDORA_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define PANDORA_NOALLOC_MAX_VERTICES 706113   /* largest n that fits, any tuning */
+PANDORA_API int pandora_dendrogram_noalloc(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                                           int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream);
+
+/*
  * Waits for hip_stream, then returns the deferred status of the
  * stream-ordered calls made on it since the last read, and clears it.
  * PANDORA_OK if none failed.  If several failed, their errors are merged and

@@ -59,6 +59,8 @@ def _load():
     vp = ctypes.c_void_p
     lib.pandora_dendrogram.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
     lib.pandora_dendrogram.restype = ctypes.c_int
+    lib.pandora_dendrogram_noalloc.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.pandora_dendrogram_noalloc.restype = ctypes.c_int
     lib.pandora_dendrogram_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
     lib.pandora_dendrogram_batched.restype = ctypes.c_int
     lib.pandora_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
@@ -199,6 +201,20 @@ def dendrogram(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
         vp = torch.empty(n, dtype=torch.int32, device=dev)
         _check(dendrogram_into(n, u, v, w, ep, vp, stream))
     return ep, vp
+
+
+# Largest tree pandora_dendrogram_noalloc accepts (its fixed scratch array).
+NOALLOC_SCRATCH_BYTES = 64 << 20
+NOALLOC_MAX_VERTICES = 706113
+
+
+def dendrogram_noalloc_into(n: int, u, v, w, edge_parent, vertex_parent, stream=None) -> int:
+    """Raw call of the entry point that allocates nothing (its scratch is a
+    fixed device array; trees above NOALLOC_MAX_VERTICES give OUT_OF_MEMORY).
+    Writes into preallocated int32 device tensors; returns the status."""
+    _apply_tuning(int(n) - 1)
+    return _load().pandora_dendrogram_noalloc(int(n), _dptr(u), _dptr(v), _dptr(w), _dptr(edge_parent),
+                                              _dptr(vertex_parent), _stream_handle(stream))
 
 
 def flat_clusters(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, min_cluster_size: int,

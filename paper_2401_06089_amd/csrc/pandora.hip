@@ -36,6 +36,20 @@
 #include "kernels.hpp"
 #include "pandora.h"
 
+// Scratch of pandora_dendrogram_noalloc: a fixed array in every GPU's memory
+// (see run_noalloc).  Its name stands for a host-side shadow in host code;
+// kernels get the device address from noalloc_symbol_address().
+static __device__ __align__(256) unsigned char scratch[PANDORA_NOALLOC_SCRATCH_BYTES];
+
+static void* noalloc_symbol_address() {   // for the current device
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
 namespace pandora {
 namespace {
 
@@ -804,6 +818,60 @@ int run_async(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v
     return rc;
 }
 
+// ---- the entry point that allocates nothing --------------------------------------
+//
+// pandora_dendrogram_noalloc keeps every byte of its scratch in the fixed
+// device array `scratch` (file scope, below the namespaces).  Each GPU holds its
+// own copy at its own address; host code never passes the array's name to a
+// kernel (that is a host-side stand-in), only the address hipGetSymbolAddress
+// returns for the current device, fetched once per device.  One lock per
+// device covers the whole blocking call, so two calls never share the array
+// at the same time.
+struct NoAllocDevice {
+    std::mutex mu;
+    void* ptr = nullptr;   // device address of `scratch` on this GPU
+};
+constexpr int kNoAllocMaxDevices = 64;
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+int run_noalloc(int64_t N, const int32_t* u, const int32_t* v, const float* w, int32_t* edge_parent,
+                int32_t* vertex_parent, hipStream_t s) {
+    int dev = 0;
+    PD_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return PANDORA_ERR_HIP;
+    NoAllocDevice& nd = g_noalloc[dev];
+    std::lock_guard<std::mutex> lock(nd.mu);
+    if (!nd.ptr) {
+        nd.ptr = noalloc_symbol_address();
+        if (!nd.ptr) return PANDORA_ERR_HIP;
+    }
+    const int64_t M = N - 1;
+    if (M == 0) {
+        PD_TRY(launch_fill_i32(vertex_parent, 1, -1, s));
+        PD_TRY(hipStreamSynchronize(s));
+        g_last = Stats{};
+        return PANDORA_OK;
+    }
+    const pandora_tuning_t tune = current_tuning();
+    const Layout L = make_layout(N, 1, tune.chain_digit_bits, tune.sort_tile_cfg);
+    if (L.total > PANDORA_NOALLOC_SCRATCH_BYTES) return PANDORA_ERR_OUT_OF_MEMORY;
+    // The control block is read back into this host copy (plain pageable
+    // memory); the level loop is the same as pandora_dendrogram's.
+    static thread_local Control hctrl;
+    const Scratch sc{nd.ptr, &hctrl};
+    Stats st;
+    struct NoEvents {   // no profiler events: creating them may allocate
+        NoEvents() { t_capturing = true; }
+        ~NoEvents() { t_capturing = false; }
+    } no_events;
+    int rc = enqueue(sc, L, tune, M <= (int64_t)tune.sync_free_max_edges, nullptr, 1, u, v, w, edge_parent,
+                     vertex_parent, s, st);
+    if (rc == PANDORA_OK) rc = finish(sc, L, 1, s, st);
+    else (void)hipStreamSynchronize(s);   // nothing may still use the array when the lock drops
+    if (rc == PANDORA_OK) g_last = st;
+    return rc;
+}
+
 // ---- HDBSCAN* flat clusters ------------------------------------------------------
 
 struct FlatLayout {
@@ -1358,6 +1426,16 @@ int pandora_dendrogram(int64_t n, const int32_t* u, const int32_t* v, const floa
     if (!ids_fit(n, 1)) return PANDORA_ERR_INVALID_ARG;
     const int64_t voff[2] = {0, n};
     return run_and_drain(voff, 1, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
+}
+
+int pandora_dendrogram_noalloc(int64_t n, const int32_t* u, const int32_t* v, const float* w,
+                               int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream) {
+    if (n < 1 || n > INT32_MAX || !vertex_parent) return PANDORA_ERR_INVALID_ARG;
+    if (n > 1 && (!u || !v || !w || !edge_parent)) return PANDORA_ERR_INVALID_ARG;
+    if (!ids_fit(n, 1)) return PANDORA_ERR_INVALID_ARG;
+    // the limit does not depend on the tuning
+    if (n > 1 && pandora_workspace_bytes(n, 1) > PANDORA_NOALLOC_SCRATCH_BYTES) return PANDORA_ERR_OUT_OF_MEMORY;
+    return run_noalloc(n, u, v, w, edge_parent, vertex_parent, static_cast<hipStream_t>(hip_stream));
 }
 
 int pandora_dendrogram_batched(int32_t B, const int64_t* voff, const int32_t* u, const int32_t* v,

@@ -41,6 +41,7 @@ def lib():
     L.pandora_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     L.pandora_last_stats.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.pandora_dendrogram_async.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 6
+    L.pandora_dendrogram_noalloc.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 6
     L.pandora_dendrogram_batched_async.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 7
     L.pandora_set_workspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     L.pandora_flat_clusters.argtypes = ([ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int32]
@@ -66,7 +67,8 @@ def test_header_declares_the_api():
                  "pandora_set_workspace", "pandora_flat_clusters", "pandora_flat_clusters_workspace_bytes",
                  "pandora_emst"):
         assert must in names
-    assert len(names) == 23
+    assert "pandora_dendrogram_noalloc" in names
+    assert len(names) == 24
 
 
 def test_library_exports_exactly_the_declared_functions(lib):
@@ -99,6 +101,14 @@ def test_argument_errors_come_back_before_any_launch(lib):
     assert lib.pandora_dendrogram(10, None, d, d, d, d, None) == INVALID_ARG
     assert lib.pandora_dendrogram(10, d, d, d, None, d, None) == INVALID_ARG
     assert lib.pandora_dendrogram(10, d, d, d, d, None, None) == INVALID_ARG
+    # the entry point with a fixed scratch array: the same checks, and trees
+    # beyond that array come back as OUT_OF_MEMORY before any launch
+    assert lib.pandora_dendrogram_noalloc(0, d, d, d, d, d, None) == INVALID_ARG
+    assert lib.pandora_dendrogram_noalloc(10, None, d, d, d, d, None) == INVALID_ARG
+    assert lib.pandora_dendrogram_noalloc(10, d, d, d, d, None, None) == INVALID_ARG
+    assert lib.pandora_dendrogram_noalloc(1_200_000_000, d, d, d, d, d, None) == INVALID_ARG
+    assert lib.pandora_dendrogram_noalloc(706_114, d, d, d, d, d, None) == 4   # OUT_OF_MEMORY
+    assert lib.pandora_dendrogram_noalloc(50_000_000, d, d, d, d, d, None) == 4
 
     def voff(*xs):
         return (ctypes.c_int64 * len(xs))(*xs)
