@@ -173,8 +173,9 @@ def main():
     ap.add_argument("--sample-every", type=int, default=4,
                     help="bracket the dominant kernel with HIP events on every k-th timed step")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 1 GiB device-to-device copy: a kernel of known traffic "
-                         "for scaling hardware byte counters")
+                    help="first run two kernels of known traffic for scaling hardware byte counters: a "
+                         "plain 1 GiB device-to-device copy, and 2^26 random 4-byte gathers from a 1 GiB "
+                         "table (each must move at least one cache line)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -196,7 +197,14 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del dst
+        g = torch.Generator(device=dev)
+        g.manual_seed(0)
+        idx = torch.randint(0, src.numel(), (1 << 26,), device=dev, generator=g)
+        torch.take(src, idx)
+        torch.cuda.synchronize()
+        del src, idx
+        torch.cuda.empty_cache()
 
     if args.workload == "c5":
         return run_serving(args, dev)
@@ -406,6 +414,7 @@ def main():
     if not args.no_extras and args.workload == "c3":
         out["c4_batched"] = side_batched(dev)
         out["c5_serving_short"] = side_serving(dev)
+        out["size_sweep"] = size_sweep(dev, items[0][1])
     if not args.no_cpu_baseline:
         oracle_baseline(out, items, args.workload)
     print(json.dumps(out), flush=True)
@@ -534,6 +543,60 @@ def side_batched(dev, reps=5):
             "batched_ms": 1000 * batched, "batched_edges_per_s": f.m_total / batched,
             "per_tree_calls_ms": 1000 * per_s, "per_tree_edges_per_s": f.m_total / per_s,
             "batched_speedup": per_s / batched, "reps": reps}
+
+
+SWEEP_SIZES = (1_000, 10_000, 100_000, 1_000_000, 10_000_000, 50_000_000)
+
+
+def size_sweep(dev, c3_tree=None, reps=5):
+    """Problem-size sweep on the two single-tree shapes (random recursive tree
+    with uniform weights; the preferential-attachment tree with lognormal
+    weights and bridges): the GPU path (median of `reps` calls, each with the
+    autotuned settings for its size) against the multithreaded CPU form of
+    the same method on every host thread (one call), both on the same inputs.
+    Shows where the GPU saturates and where it overtakes the CPU."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_2401_06089_amd as pd
+    from paper_2401_06089_amd import cpu as pcpu
+    threads = host_threads()
+    rows = []
+    for shape in ("rrt", "pa"):
+        for n in SWEEP_SIZES:
+            if shape == "pa" and n == 50_000_000 and c3_tree is not None:
+                t = c3_tree
+            elif shape == "pa":
+                t = gen.c3_pref_attach(0, n=n)
+            else:
+                t = gen.rrt(n, 0)
+            u = torch.from_numpy(t.u).to(dev)
+            v = torch.from_numpy(t.v).to(dev)
+            w = torch.from_numpy(t.w).to(dev)
+            ep = torch.empty(t.m, dtype=torch.int32, device=dev)
+            vp = torch.empty(t.n, dtype=torch.int32, device=dev)
+            for _ in range(2):
+                st = pd.dendrogram_into(t.n, u, v, w, ep, vp)
+                if st != pd.OK:
+                    raise RuntimeError(pd.status_string(st))
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                a = time.perf_counter()
+                pd.dendrogram_into(t.n, u, v, w, ep, vp)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - a)
+            gpu_s = statistics.median(ts)
+            a = time.perf_counter()
+            cep, cvp = pcpu.dendrogram(t.n, t.u, t.v, t.w, threads=threads)
+            cpu_s = time.perf_counter() - a
+            same = bool(np.array_equal(cep, ep.cpu().numpy()) and np.array_equal(cvp, vp.cpu().numpy()))
+            rows.append({"shape": shape, "n": t.n, "gpu_ms": 1000 * gpu_s, "gpu_edges_per_s": t.m / gpu_s,
+                         "cpu_mt_ms": 1000 * cpu_s, "cpu_mt_edges_per_s": t.m / cpu_s,
+                         "gpu_over_cpu_mt": cpu_s / gpu_s, "same_result": same})
+            del u, v, w, ep, vp
+    torch.cuda.empty_cache()
+    return {"cpu_threads": threads, "host_cpu": cpu_model(), "rows": rows}
 
 
 def side_serving(dev):
