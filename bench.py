@@ -165,7 +165,7 @@ def main():
     ap.add_argument("--discard", type=float, default=5.0, help="c5: warm-up seconds not reported")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5: arrivals per second")
     ap.add_argument("--pool", type=int, default=512, help="c5: distinct trees in the device pool")
-    ap.add_argument("--streams", type=int, default=4, help="c5: server worker streams")
+    ap.add_argument("--streams", type=int, default=2, help="c5: server slots (one stream each)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="c5: admission budget")
     ap.add_argument("--max-batch-edges", type=int, default=8_000_000, help="c5: edge cap of one batch")
     ap.add_argument("--policy", default="small_first", choices=["fifo", "small_first"], help="c5: batching order")
@@ -602,7 +602,7 @@ def size_sweep(dev, c3_tree=None, reps=5):
 def side_serving(dev):
     """A short open-loop serving run (the c5 mix at 2,000 requests/s) from a
     smaller device pool."""
-    ns = argparse.Namespace(rate=2000.0, duration=15.0, discard=3.0, pool=96, streams=4, budget_gb=200.0,
+    ns = argparse.Namespace(rate=2000.0, duration=15.0, discard=3.0, pool=96, streams=2, budget_gb=200.0,
                             max_batch_edges=8_000_000, policy="small_first")
     r = run_serving(ns, dev, emit=False)
     return {"workload": "c5", "duration_s": ns.duration, "discarded_s": ns.discard, "pool_trees": ns.pool,
@@ -737,7 +737,9 @@ def run_serving(args, dev, emit=True):
         srv.submit(r)
     for r in warm:
         r.future.result()
-    srv.done.clear()
+    with srv.cv:
+        srv.done.clear()
+        srv.batches = 0
 
     # The client consumes each result as it completes (here: checks it and
     # drops it), so device memory holds only what is in flight.
@@ -794,8 +796,10 @@ def run_serving(args, dev, emit=True):
                        "mean": stats.get("mean_ms"), "max": stats.get("max_ms"), "per": "request"},
         "requests": {"submitted": len(reqs), "measured": stats.get("count"),
                      "offered_edges_per_s": float(sum(pool[int(p)][0] - 1 for p in picks) / args.duration),
-                     "batches": srv.batches, "max_concurrent_batches": srv.max_concurrent,
-                     "peak_admitted_bytes": srv.peak_in_use, "wall_s": end - start},
+                     "batches": srv.batches, "requests_per_batch": len(reqs) / max(srv.batches, 1),
+                     "max_concurrent_batches": srv.max_concurrent,
+                     "reserved_bytes": srv.reserved, "peak_admitted_bytes": srv.peak_in_use,
+                     "wall_s": end - start},
     }
     del pool
     torch.cuda.empty_cache()

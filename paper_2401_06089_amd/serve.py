@@ -1,16 +1,25 @@
 """Continuous-batching request server for dendrogram builds on one GPU.
 
-Requests (one tree each, device-resident u, v, w) are admitted by their HBM
-footprint against a byte budget: the library's scratch bytes for the tree
-(``pandora_workspace_bytes``) plus its inputs and outputs.  Each of S worker
-threads owns a HIP stream.  When a worker is free it takes every admitted
-request that is waiting (up to an edge cap), concatenates them into one
-forest on its stream, builds all their dendrograms with one batched call,
-hands each request its slice of the outputs, and releases the bytes.
-Requests that arrive while other batches run are admitted as bytes free up,
-and batches on different streams overlap on the device.  A forest call gives
-every tree exactly the result it gets alone, so a request's answer does not
-depend on what it was batched with.
+Requests (one tree each, device-resident u, v, w) wait in a queue.  Each of S
+slots owns a worker thread, a HIP stream, a caller-owned library workspace and
+an input arena, allocated once and sized for the largest batch; the byte
+budget covers those reservations plus the outputs of every admitted request,
+so it bounds the device memory the server uses.
+
+A free slot takes the waiting requests that fit (budget, edge cap, tree cap;
+in arrival order, or smallest first behind the oldest), copies their inputs
+into its arena (one copy kernel per array; a lone request is read in place)
+and builds all their dendrograms with one batched call on its stream.
+Requests that arrive while the slots are busy wait and are admitted together
+as slots free up, so batches grow with the load, and batches on different
+slots overlap on the device.  The batched call picks its level loop by size
+(exact grids with a small read-back per level for large batches, the
+host-free loop below the tuned threshold), which measured faster here than
+the stream-ordered call for every batch: the host-free loop has to size
+every grid by the level bounds.  A forest call gives every tree exactly the
+result it gets alone, so a request's answer does not depend on what it was
+batched with.  If a batch reports an input error, its requests are rebuilt
+one by one so that the error reaches only the request that caused it.
 """
 from __future__ import annotations
 
@@ -24,7 +33,7 @@ from typing import List, Optional
 import numpy as np
 import torch
 
-from . import dendrogram_batched, workspace_bytes
+from . import PandoraError, dendrogram, dendrogram_batched, set_workspace, workspace_bytes
 
 
 @dataclass
@@ -37,6 +46,7 @@ class Request:
     arrival: float                     # scheduled arrival (perf_counter seconds)
     footprint: int = 0
     ready: Optional[torch.cuda.Event] = None   # inputs written (recorded at submit)
+    stream: Optional[torch.cuda.Stream] = None  # the submitting stream (receives the outputs)
     future: Future = field(default_factory=Future)
     admitted: float = 0.0
     started: float = 0.0
@@ -44,50 +54,93 @@ class Request:
 
 
 def request_footprint(n: int) -> int:
-    """HBM bytes one tree occupies while it is built: scratch + inputs + outputs."""
-    io = 12 * (n - 1) + 4 * (n - 1) + 4 * n
-    return workspace_bytes(n, 1) + io
+    """Device bytes one admitted request holds until its client drops the
+    result: its outputs (edge_parent and vertex_parent).  Scratch and input
+    arenas belong to the slots and are reserved once."""
+    return 4 * (n - 1) + 4 * n
+
+
+def slot_bytes(max_edges: int, max_trees: int) -> int:
+    """Bytes one slot reserves: the library workspace for any batch of at most
+    max_edges edges over max_trees trees, plus the u, v, w input arena."""
+    return workspace_bytes(max_edges + max_trees, max_trees) + 12 * max_edges
+
+
+@dataclass
+class _Slot:
+    stream: torch.cuda.Stream
+    workspace: torch.Tensor
+    u: torch.Tensor
+    v: torch.Tensor
+    w: torch.Tensor
+    busy: bool = False
 
 
 class DendrogramServer:
-    def __init__(self, budget_bytes: int, streams: int = 4, max_batch_edges: int = 64 << 20,
-                 device: int = 0, policy: str = "fifo"):
+    def __init__(self, budget_bytes: int, streams: int = 2, max_batch_edges: int = 8 << 20,
+                 device: int = 0, policy: str = "small_first", max_batch_trees: int = 4096,
+                 max_tree_vertices: int = 1 << 24):
         if policy not in ("fifo", "small_first"):
             raise ValueError(f"unknown policy {policy!r}")
         self.policy = policy
-        self.peak_in_use = 0
         self.budget = int(budget_bytes)
         self.max_batch_edges = int(max_batch_edges)
+        self.max_batch_trees = int(max_batch_trees)
+        # a lone request may exceed the batch edge cap, up to the largest tree
+        # the slots are sized for
+        self.max_tree_vertices = int(max_tree_vertices)
+        self.slot_edges = max(self.max_batch_edges, self.max_tree_vertices - 1)
         self.device = torch.device("cuda", device)
         self.pending: collections.deque[Request] = collections.deque()
         self.cv = threading.Condition()
         self.in_use = 0
+        self.peak_in_use = 0
         self.closed = False
         self.done: List[Request] = []
         self.batches = 0
         self.max_concurrent = 0
         self._running = 0
-        self.workers = [threading.Thread(target=self._worker, args=(i,), daemon=True)
-                        for i in range(streams)]
-        for t in self.workers:
+        self.slots: List[_Slot] = []
+        per_slot = slot_bytes(self.slot_edges, self.max_batch_trees) if streams > 0 else 0
+        self.reserved = per_slot * streams
+        if self.reserved > self.budget:
+            raise ValueError(f"{streams} slots need {self.reserved} bytes, budget is {self.budget}")
+        for _ in range(streams):
+            with torch.cuda.device(self.device):
+                st = torch.cuda.Stream(device=self.device)
+                ws = torch.empty(per_slot - 12 * self.slot_edges, dtype=torch.uint8, device=self.device)
+                set_workspace(ws, stream=st)
+                self.slots.append(_Slot(st, ws,
+                                        torch.empty(self.slot_edges, dtype=torch.int32, device=self.device),
+                                        torch.empty(self.slot_edges, dtype=torch.int32, device=self.device),
+                                        torch.empty(self.slot_edges, dtype=torch.float32, device=self.device)))
+        self.threads = [threading.Thread(target=self._worker, args=(s,), daemon=True) for s in self.slots]
+        for t in self.threads:
             t.start()
 
     # ---- client side ------------------------------------------------------------
     def submit(self, req: Request) -> Future:
         """Queue one tree.  Its tensors may still be being written by work on the
-        submitting thread's current stream: the worker's stream waits for that
-        work before reading them."""
+        submitting thread's current stream: the slot's stream waits for that
+        work before reading them, and the outputs are tied to that stream."""
         req.footprint = request_footprint(req.n)
         if isinstance(req.w, torch.Tensor) and req.w.is_cuda:
+            req.stream = torch.cuda.current_stream(self.device)
             req.ready = torch.cuda.Event()
-            req.ready.record(torch.cuda.current_stream(self.device))
+            req.ready.record(req.stream)
         with self.cv:
             if self.closed:
                 req.future.set_exception(RuntimeError("the server is closed"))
                 return req.future
-            if req.footprint > self.budget:
+            if req.footprint + self.reserved > self.budget:
                 req.future.set_exception(MemoryError(
-                    f"request {req.rid} needs {req.footprint} bytes, budget is {self.budget}"))
+                    f"request {req.rid} needs {req.footprint} bytes beyond the {self.reserved} reserved, "
+                    f"budget is {self.budget}"))
+                return req.future
+            if req.n > self.max_tree_vertices:
+                req.future.set_exception(MemoryError(
+                    f"request {req.rid} has {req.n} vertices, the slots hold trees of at most "
+                    f"{self.max_tree_vertices}"))
                 return req.future
             self.pending.append(req)
             self.cv.notify_all()
@@ -97,16 +150,18 @@ class DendrogramServer:
         with self.cv:
             self.closed = True
             self.cv.notify_all()
-        for t in self.workers:
+        for t in self.threads:
             t.join()
+        for s in self.slots:
+            set_workspace(None, stream=s.stream)
 
-    # ---- workers -----------------------------------------------------------------
+    # ---- batching policy ------------------------------------------------------------
     def _take_batch(self) -> Optional[List[Request]]:
-        """Under the lock: admit waiting requests while they fit the byte budget
-        and the batch edge cap.  "fifo" takes them in arrival order and stops at
-        the first that does not fit; "small_first" takes the smallest waiting
-        requests first (the oldest request always heads the batch, so none
-        waits behind an endless stream of smaller ones)."""
+        """Under the lock: admit waiting requests while they fit the byte budget,
+        the batch edge cap and the tree cap.  "fifo" takes them in arrival
+        order and stops at the first that does not fit; "small_first" takes
+        the smallest waiting requests first (the oldest request always heads
+        the batch, so none waits behind an endless stream of smaller ones)."""
         if not self.pending:
             return None
         if self.policy == "fifo":
@@ -119,14 +174,14 @@ class DendrogramServer:
         edges = 0
         for i in order:
             r = self.pending[i]
-            if batch and edges + (r.n - 1) > self.max_batch_edges:
+            if batch and (edges + (r.n - 1) > self.max_batch_edges or len(batch) >= self.max_batch_trees):
                 if self.policy == "fifo":
                     break
                 continue
-            if self.in_use + r.footprint > self.budget:
+            if self.reserved + self.in_use + r.footprint > self.budget:
                 break
             self.in_use += r.footprint
-            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            self.peak_in_use = max(self.peak_in_use, self.reserved + self.in_use)
             r.admitted = time.perf_counter()
             batch.append(r)
             taken.append(i)
@@ -136,12 +191,11 @@ class DendrogramServer:
             self.pending = collections.deque(r for i, r in enumerate(self.pending) if i not in keep)
         return batch or None
 
-    def _worker(self, idx: int):
+    # ---- slot workers ------------------------------------------------------------------
+    def _worker(self, slot: _Slot):
         torch.cuda.set_device(self.device)
-        stream = torch.cuda.Stream(device=self.device)
         while True:
             with self.cv:
-                batch = None
                 while True:
                     batch = self._take_batch()
                     if batch is not None or (self.closed and not self.pending):
@@ -149,46 +203,65 @@ class DendrogramServer:
                     self.cv.wait(timeout=0.05)
                 if batch is None:
                     return
+                slot.busy = True
                 self._running += 1
                 self.max_concurrent = max(self.max_concurrent, self._running)
             try:
-                self._run_batch(batch, stream)
+                self._run_batch(slot, batch)
             except Exception as e:   # surface the failure on every request of the batch
                 for r in batch:
                     if not r.future.done():
                         r.future.set_exception(e)
             finally:
                 with self.cv:
+                    slot.busy = False
                     self._running -= 1
                     self.batches += 1
                     for r in batch:
                         self.in_use -= r.footprint
+                    self.done.extend(batch)
                     self.cv.notify_all()
 
-    def _run_batch(self, batch: List[Request], stream: torch.cuda.Stream):
+    def _run_batch(self, slot: _Slot, batch: List[Request]):
         start = time.perf_counter()
         sizes = np.array([r.n for r in batch], dtype=np.int64)
         voff = np.zeros(len(batch) + 1, dtype=np.int64)
         np.cumsum(sizes, out=voff[1:])
-        with torch.cuda.stream(stream):
+        E = int(voff[-1]) - len(batch)
+        with torch.cuda.stream(slot.stream):
             for r in batch:
                 if r.ready is not None:
-                    stream.wait_event(r.ready)
+                    slot.stream.wait_event(r.ready)
             if len(batch) == 1:
                 u, v, w = batch[0].u, batch[0].v, batch[0].w
             else:
-                u = torch.cat([r.u for r in batch])
-                v = torch.cat([r.v for r in batch])
-                w = torch.cat([r.w for r in batch])
-            ep, vp = dendrogram_batched(voff, u, v, w, stream=stream)
+                u, v, w = slot.u[:E], slot.v[:E], slot.w[:E]
+                torch.cat([r.u for r in batch], out=u)
+                torch.cat([r.v for r in batch], out=v)
+                torch.cat([r.w for r in batch], out=w)
+            try:
+                ep, vp = dendrogram_batched(voff, u, v, w, stream=slot.stream)
+                results = [(ep[int(voff[b]) - b:int(voff[b + 1]) - b - 1], vp[int(voff[b]):int(voff[b + 1])])
+                           for b in range(len(batch))]
+            except PandoraError:
+                # an input error somewhere in the batch: rebuild each tree alone
+                results = []
+                for r in batch:
+                    try:
+                        results.append(dendrogram(r.u, r.v, r.w, n=r.n, stream=slot.stream))
+                    except PandoraError as e:
+                        results.append(e)
         finished = time.perf_counter()
-        for b, r in enumerate(batch):
-            v0, v1 = int(voff[b]), int(voff[b + 1])
+        for r, res in zip(batch, results):
             r.started = start
             r.finished = finished
-            r.future.set_result((ep[v0 - b:v1 - b - 1], vp[v0:v1]))
-        with self.cv:
-            self.done.extend(batch)
+            if isinstance(res, Exception):
+                r.future.set_exception(res)
+                continue
+            if r.stream is not None:   # the client's stream may still use them when it drops them
+                for t in res:
+                    t.record_stream(r.stream)
+            r.future.set_result(res)
 
 
 def latency_stats(reqs: List[Request], warmup_s: float, t0: float) -> dict:

@@ -22,10 +22,28 @@ def take(srv):
     return [r.rid for r in b] if b else None
 
 
-def test_footprint_grows_with_size():
+def test_footprint_is_the_outputs():
     f = [request_footprint(n) for n in (10, 1000, 100_000, 10_000_000)]
     assert all(a < b for a, b in zip(f, f[1:]))
-    assert f[-1] > 10_000_000 * 60
+    assert f[-1] == 4 * (10_000_000 - 1) + 4 * 10_000_000    # edge_parent + vertex_parent
+
+
+def test_tree_cap_limits_a_batch():
+    srv = DendrogramServer(10**12, streams=0, max_batch_edges=10**9, max_batch_trees=3, policy="fifo")
+    for i in range(7):
+        srv.submit(Request(i, 100, None, None, None, arrival=float(i)))
+    assert take(srv) == [0, 1, 2]
+    assert take(srv) == [3, 4, 5]
+    assert take(srv) == [6]
+
+
+def test_tree_larger_than_the_slots_is_rejected_at_submit():
+    srv = DendrogramServer(10**12, streams=0, max_tree_vertices=1000)
+    r = Request(0, 1001, None, None, None, arrival=0.0)
+    srv.submit(r)
+    with pytest.raises(MemoryError):
+        r.future.result(timeout=1)
+    assert take(srv) is None
 
 
 def test_fifo_takes_arrival_order_up_to_the_edge_cap():
