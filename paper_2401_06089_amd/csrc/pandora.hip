@@ -126,6 +126,22 @@ int ceil_log2(int64_t x) {   // smallest L with 2^L >= x (x >= 1)
     return L;
 }
 
+// Digit width and pass count of the chain sort for chain keys in
+// [0, key_range): as few passes of 9-bit digits as cover them, with 8-bit
+// digits whenever those need no more passes (or the width the tuning fixes).
+void chain_digits(int64_t key_range, int pref, int* bits_out, int* passes_out) {
+    int bits = 0;
+    while ((int64_t(1) << bits) < std::max<int64_t>(key_range, 1)) ++bits;
+    if (pref == 8 || pref == 9) {
+        *bits_out = pref;
+        *passes_out = std::max(1, (bits + pref - 1) / pref);
+        return;
+    }
+    const int p8 = std::max(1, (bits + 7) / 8), p9 = std::max(1, (bits + 8) / 9);
+    *bits_out = p9 < p8 ? 9 : 8;
+    *passes_out = p9 < p8 ? p9 : p8;
+}
+
 Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg = kDefaultSortCfg) {
     Layout L;
     L.N = N;
@@ -146,24 +162,14 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
     }
     L.flat_cap = 0;
     for (int64_t c : L.capV) L.flat_cap += c;
-    const int64_t key_range = std::max<int64_t>(L.flat_cap - N, 1);
-    int bits = 0;
-    while ((int64_t(1) << bits) < key_range) ++bits;
-    // Chain keys need `bits` bits: as few passes of 9-bit digits as cover
-    // them, with 8-bit digits whenever those cover the same pass count.
-    if (chain_bits_pref == 8 || chain_bits_pref == 9) {
-        L.chain_bits = chain_bits_pref;
-        L.chain_passes = std::max(1, (bits + chain_bits_pref - 1) / chain_bits_pref);
-    } else {
-        const int p8 = std::max(1, (bits + 7) / 8), p9 = std::max(1, (bits + 8) / 9);
-        L.chain_bits = p9 < p8 ? 9 : 8;
-        L.chain_passes = p9 < p8 ? p9 : p8;
-    }
+    chain_digits(L.flat_cap - N, chain_bits_pref, &L.chain_bits, &L.chain_passes);
 
     const int64_t E1 = std::max<int64_t>(L.capE[1], 1), E2 = std::max<int64_t>(L.capE[2], 1);
     L.sort_cfg = sort_cfg;
     L.lb_words_w = sort_tiles(std::max<int64_t>(M, 1), sort_cfg) * 256;
-    L.lb_words_c = sort_tiles(std::max<int64_t>(M, 1), sort_cfg) * (int64_t(1) << L.chain_bits);
+    // room for 9-bit chain digits whatever the capacity suggests: a call may
+    // pick its digits from the level sizes it finds (see enqueue)
+    L.lb_words_c = sort_tiles(std::max<int64_t>(M, 1), sort_cfg) * (int64_t(1) << kMaxRadixBits);
     const int64_t sortlb = std::max(L.lb_words_w, L.lb_words_c);
     const int64_t scant = scan_tiles(std::max<int64_t>(M, 1));
     size_t c = 0;
@@ -231,6 +237,7 @@ std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
 struct Stats {
     int64_t levels = 0, sum_edges = 0, jump_launches = 0, tail_levels = 0, tail_entry_edges = 0,
             sync_free = 0, persistent = 0;
+    int chain_passes = 0;   // passes the chain sort ran (its output ends in K1/V1 when odd, else K0/V0)
 };
 thread_local Stats g_last;
 
@@ -542,9 +549,10 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
     };
     const int64_t persist_max = tune.persist_max_edges;
     st.sync_free = sync_free ? 1 : 0;
+    int chain_bits = L.chain_bits, chain_passes = L.chain_passes;
     if (!sync_free) {
         // Host-driven: exact grids, pointer jumping relaunched until it converges.
-        int64_t m = M, n = N;
+        int64_t m = M, n = N, off = 0;
         int j = 0;
         while (!tail_level(m, n, kTailE, kTailV)) {
             if (j >= L.Lmax) return PANDORA_ERR_NOT_A_TREE;
@@ -574,10 +582,19 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
                 return PANDORA_ERR_NOT_A_TREE;
             PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 40.0 * m_next, launch_compact(a, s));
+            off += n;
             n = n_next;
             m = m_next;
             ++j;
         }
+        // Chain keys are flat ids above level 0.  The levels from here on
+        // (persistent kernel, LDS tail) hold fewer than 2(n + B) + 2 vertices
+        // in all: a level has at most (m + B) / 2 leaf edges, one vertex each
+        // above it.  So the keys lie below this bound, usually far below the
+        // capacity-based one, and the chain sort may need fewer or narrower
+        // digits.
+        const int64_t bound = std::max<int64_t>(off - N, 0) + 2 * (n + B) + 66;
+        if (bound < L.flat_cap - N) chain_digits(bound, tune.chain_digit_bits, &chain_bits, &chain_passes);
     } else {
         // Sync-free: every level that could exceed the LDS tail is launched with
         // capacity-sized grids; levels that turn out small or empty return at
@@ -630,22 +647,24 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         wa.flat_cap = L.flat_cap;
         wa.svflat = svflat;
         wa.vinfo_all = vinfo_all;
-        wa.bits = L.chain_bits;
+        wa.bits = chain_bits;
         wa.ckey = K[0];
         wa.hist_row = 4;
-        wa.passes = L.chain_passes;
+        wa.passes = chain_passes;
         wa.lb_zero = LB[0];
-        wa.lb_zero_words = L.lb_words_c;
+        const int64_t lbw_c = sort_tiles(M, L.sort_cfg) << chain_bits;
+        wa.lb_zero_words = lbw_c;
         wa.ctrl = ctrl;
         PD_TIMED(PK_WALK_HIST, 12.0 * M, launch_walk_hist(wa, s));
         const uint32_t* kin = K[0];
         const int32_t* vin = perm;
-        for (int p = 0; p < L.chain_passes; ++p) {
+        st.chain_passes = chain_passes;
+        for (int p = 0; p < chain_passes; ++p) {
             SortPassArgs a{};
             a.n = M;
             a.cfg = L.sort_cfg;
-            a.bits = L.chain_bits;
-            a.shift = L.chain_bits * p;
+            a.bits = chain_bits;
+            a.shift = chain_bits * p;
             a.pass = 4 + p;
             a.keys_in = kin;
             a.vals_in = vin;
@@ -653,7 +672,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             a.vals_out = V[(p + 1) & 1];
             a.lb = LB[p & 1];
             a.lb_zero = LB[(p + 1) & 1];
-            a.lb_zero_words = L.lb_words_c;
+            a.lb_zero_words = lbw_c;
             a.ctrl = ctrl;
             PD_TIMED(PK_SORT_C_PASS, 16.0 * M, launch_sort_pass(SRC_KEYS, DST_KEYS, a, s));
             kin = K[(p + 1) & 1];
@@ -985,8 +1004,8 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
     a.n = N;
     a.m = M;
     a.mcs = mcs;
-    a.skey = at<uint32_t>(ws.dev, (L.chain_passes & 1) ? L.K1 : L.K0);
-    a.sid = at<int32_t>(ws.dev, (L.chain_passes & 1) ? L.V1 : L.V0);
+    a.skey = at<uint32_t>(ws.dev, (st.chain_passes & 1) ? L.K1 : L.K0);
+    a.sid = at<int32_t>(ws.dev, (st.chain_passes & 1) ? L.V1 : L.V0);
     a.ep = edge_parent;
     a.vp = vertex_parent;
     a.w = w;
