@@ -137,6 +137,28 @@ def copy_bandwidth(dev) -> float:
     return gbps
 
 
+def random_gather_rate(dev) -> dict:
+    """The rate of independent random 4-byte gathers from a 1 GiB table on this
+    GPU (torch.take of 2^26 uniform indices): the ceiling of kernels bound by
+    random accesses, each of which moves a whole cache line."""
+    import torch
+    table = torch.zeros(1 << 28, dtype=torch.int32, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    idx = torch.randint(0, table.numel(), (1 << 26,), device=dev, generator=g)
+    torch.take(table, idx)
+    torch.cuda.synchronize()
+    reps = 3
+    a = time.perf_counter()
+    for _ in range(reps):
+        torch.take(table, idx)
+    torch.cuda.synchronize()
+    s = (time.perf_counter() - a) / reps
+    del table, idx
+    torch.cuda.empty_cache()
+    return {"gathers_per_s": (1 << 26) / s, "table_bytes": 1 << 30}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -366,6 +388,11 @@ def main():
         out["path_hbm"]["traffic_frac"] = out["path_hbm"]["traffic_GBps"] / HBM_PEAK_GBS
         out["path_hbm"]["traffic_source"] = prof_md
     out["roofline"]["copy_GBps"] = copy_bandwidth(dev)
+    rg = random_gather_rate(dev)
+    if prof and prof.get("calibration", {}).get("gather_bytes_per_access"):
+        rg["line_bytes"] = prof["calibration"]["gather_bytes_per_access"]
+        rg["line_GBps"] = rg["gathers_per_s"] * rg["line_bytes"] / 1e9
+    out["roofline"]["random_gather"] = rg
     tr = committed_traffic(args.workload, dominant)
     if tr:
         out["roofline"]["traffic"] = tr["bytes_per_launch"]
