@@ -10,7 +10,9 @@
 // the flat vertex numbering the walk is a pointer chase
 //   x <- svflat[r];  while (r >= vinfo[x].minInc) x <- vinfo[x].label;
 // and the final x identifies the chain (k_walk_hist, which also histograms
-// the chain keys for the sort that follows).
+// the chain keys for the sort that follows).  A leaf edge is lighter than
+// every alpha edge of its supervertex, so it always stays there: the level
+// kernels flag its record and the walk takes it as it is.
 //
 // Chain construction.  A stable sort of ranks by chain key lists every chain
 // lightest first.  Each edge's parent is the next, heavier edge of its chain;
@@ -35,13 +37,16 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_hist(WalkArgs a) {
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
     for (int64_t r = t0; r < a.m; r += stride) {
-        int64_t x = a.svflat[r];
+        const int32_t sv = a.svflat[r];
+        int64_t x = sv & ~kLabelFlag;
+        // a flagged record is a leaf edge, whose chain is its supervertex
         for (int it = 0;; ++it) {
             if (x < a.n0 || x >= a.flat_cap || it >= kWalkLimit) {
                 bad = true;
                 x = a.n0;
                 break;
             }
+            if (sv & kLabelFlag) break;
             const VInfo vi = a.vinfo_all[x];
             if (r < (int64_t)vi.minInc) break;
             x = vi.label;

@@ -91,6 +91,8 @@ struct alignas(8) VInfo {
 
 constexpr uint64_t kNoEdge = ~0ull;          // min64 of a vertex without edges
 constexpr int32_t kLabelFlag = INT32_MIN;    // ptr word holding a final label
+constexpr int32_t kOtherEnd = 1 << 30;       // ... held by the larger endpoint of a leaf edge
+                                             // (labels of a level are below 2^30)
 
 // Level kernels read their sizes from Control::lv[level] on the device, so a
 // level can be launched before the host knows how large it is; grids are
@@ -117,6 +119,7 @@ struct LevelArgs {
     int32_t cap_next_e;
     int32_t cap_next_v;
     int32_t* svflat;           // per rank: flat id of the supervertex the edge is contracted into
+                               // (kLabelFlag set on a leaf edge: its chain is that supervertex)
     int32_t* vertex_parent;    // level 0 output (tree-local edge ids)
     Control* ctrl;
     int jump_steps;

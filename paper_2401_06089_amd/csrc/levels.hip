@@ -207,13 +207,14 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
 
     uint32_t lmask = 0;
     uint32_t lpre[kScanItems];
-    int32_t root[kScanItems];
+    int32_t root[kScanItems], other[kScanItems];
     bool selfloop = false;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t idx = base + k * kScanBlock + tid;
         bool al = false, lf = false;
         root[k] = 0;
+        other[k] = 0;
         if (idx < L.m) {
             const uint16_t o = a.own[idx];
             a.own[idx] = 0;
@@ -223,6 +224,7 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
             al = o == 0;
             lf = o == 0x0101;
             root[k] = e.u < e.v ? e.u : e.v;
+            other[k] = e.u < e.v ? e.v : e.u;
             store_stream(a.alpha + idx, (uint8_t)(al ? 1 : 0));
         }
         const uint64_t ba = ballot(al);
@@ -278,12 +280,16 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
         }
     }
     __syncthreads();
+    // Both endpoints of a leaf edge receive the label of their supervertex
+    // (the larger one marked as such), so pointer jumping stops at either.
     const int64_t leaf_base = (int64_t)(s_excl & kLow31);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (lmask & (1u << k)) {
             const int64_t pos = leaf_base + s_cl[k][wave] + lpre[k];
-            a.ptr[root[k]] = kLabelFlag | (int32_t)pos;
+            const int32_t word = kLabelFlag | (int32_t)pos;
+            a.ptr[root[k]] = word;
+            a.ptr[other[k]] = word | kOtherEnd;
         }
     }
 }
@@ -308,8 +314,16 @@ __device__ __forceinline__ void jump_item(const LevelArgs& a, const LevelView& L
     }
     int32_t q = a.ptr[x];
     int32_t lab;
+    // In the first round only the two endpoints of a leaf edge start with a
+    // label (the classification wrote it), and their lightest edge is that
+    // leaf edge.  It is lighter than every alpha edge of its supervertex, so
+    // its chain is that supervertex itself: the smaller endpoint writes its
+    // expansion record with the flag bit set (the walk then skips it), the
+    // larger one writes nothing.
+    const bool leaf_end = round == 0 && (q & kLabelFlag);
+    const bool leaf_root = leaf_end && !(q & kOtherEnd);
     if (q & kLabelFlag) {
-        lab = q & ~kLabelFlag;
+        lab = q & ~(kLabelFlag | kOtherEnd);
     } else {
         int32_t t = a.ptr[q];
         for (int s = 0; !(t & kLabelFlag) && s < steps; ++s) {
@@ -321,12 +335,13 @@ __device__ __forceinline__ void jump_item(const LevelArgs& a, const LevelView& L
             atomicOr(&a.ctrl->not_converged, 1u << (round & 31));
             return;
         }
-        lab = t & ~kLabelFlag;
+        lab = t & ~(kLabelFlag | kOtherEnd);
         a.ptr[x] = t;                            // x now holds its label directly
     }
     const int32_t flat = (int32_t)(L.off_next + lab);
     vinfo[x].label = flat;
-    a.svflat[r] = flat;                          // the lightest edge of x falls into this supervertex
+    if (leaf_root) a.svflat[r] = flat | kLabelFlag;
+    else if (!leaf_end) a.svflat[r] = flat;      // the lightest edge of x falls into this supervertex
 }
 
 // Sizes of the level after a (written by its classification), clamped.
