@@ -110,6 +110,7 @@ struct Forest {
 // sequential stores, and slower for random or run-scattered stores, which
 // therefore keep the default policy.
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 template <typename T>
 __device__ __forceinline__ T load_stream(const T* p) { return __builtin_nontemporal_load(p); }
 template <typename T>

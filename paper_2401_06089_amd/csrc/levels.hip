@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
         e.u = (int32_t)(v0 + x);
         e.v = (int32_t)(v0 + y);
         e.id = (int32_t)i;
-        store_stream(reinterpret_cast<i32x4*>(a.E + i), i32x4{e.u, e.v, e.r, e.id});
+        store_stream(reinterpret_cast<i32x2*>(a.E) + i, i32x2{e.u, e.v});
     } else {
         e = a.E[i];
     }
@@ -157,6 +157,13 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
     // redundant atomic, never a missed one.
     if (a.min64[e.u] > key) atomicMin((unsigned long long*)&a.min64[e.u], (unsigned long long)key);
     if (a.min64[e.v] > key) atomicMin((unsigned long long*)&a.min64[e.v], (unsigned long long)key);
+}
+
+// Level 0 keeps only the endpoints of each edge (8 bytes): its id is its
+// position and its rank sits in the rank array.  Deeper levels keep 16-byte
+// records (endpoints, rank).
+__device__ __forceinline__ const i32x2* level0_recs(const LevelArgs& a) {
+    return reinterpret_cast<const i32x2*>(a.E);
 }
 
 // ---- per-item and per-tile bodies ---------------------------------------------
@@ -182,7 +189,13 @@ __device__ __forceinline__ void own_item(const LevelArgs& a, const LevelView& L,
         raise_err(a.ctrl, kErrOverflow);
         return;
     }
-    const EdgeRec e = a.E[pos];
+    EdgeRec e;
+    if (L0) {
+        const i32x2 uv = level0_recs(a)[pos];
+        e = EdgeRec{uv.x, uv.y, 0, (int32_t)pos};
+    } else {
+        e = a.E[pos];
+    }
     const int side = (e.u == (int32_t)x) ? 0 : 1;
     a.ptr[x] = side ? e.u : e.v;
     reinterpret_cast<uint8_t*>(a.own)[2 * (int64_t)pos + side] = 1;
@@ -218,8 +231,14 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
         if (idx < L.m) {
             const uint16_t o = a.own[idx];
             a.own[idx] = 0;
-            const i32x4 ev = load_stream(reinterpret_cast<const i32x4*>(a.E + idx));
-            const EdgeRec e{ev.x, ev.y, ev.z, ev.w};
+            EdgeRec e;
+            if (L0) {
+                const i32x2 uv = load_stream(level0_recs(a) + idx);
+                e = EdgeRec{uv.x, uv.y, 0, 0};
+            } else {
+                const i32x4 ev = load_stream(reinterpret_cast<const i32x4*>(a.E + idx));
+                e = EdgeRec{ev.x, ev.y, ev.z, ev.w};
+            }
             selfloop |= e.u == e.v;
             al = o == 0;
             lf = o == 0x0101;
@@ -408,8 +427,14 @@ __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView
     for (int k = 0; k < kScanItems; ++k) {
         if (!(amask & (1u << k))) continue;
         const int64_t idx = base + k * kScanBlock + tid;
-        const i32x4 ev = load_stream(reinterpret_cast<const i32x4*>(a.E + idx));
-        const EdgeRec e{ev.x, ev.y, ev.z, ev.w};
+        EdgeRec e;
+        if (L0) {
+            const i32x2 uv = load_stream(level0_recs(a) + idx);
+            e = EdgeRec{uv.x, uv.y, load_stream(a.rank + idx), (int32_t)idx};
+        } else {
+            const i32x4 ev = load_stream(reinterpret_cast<const i32x4*>(a.E + idx));
+            e = EdgeRec{ev.x, ev.y, ev.z, ev.w};
+        }
         const int32_t lx = vinfo[e.u].label;
         const int32_t ly = vinfo[e.v].label;
         const int64_t pos = abase + s_ca[k][wave] + apre[k];

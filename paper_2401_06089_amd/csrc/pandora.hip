@@ -183,7 +183,7 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
     L.V1 = take(c, 4 * M);
     L.perm = take(c, 4 * M);
     L.rank = take(c, 4 * M);
-    L.E0 = take(c, sizeof(EdgeRec) * M);
+    L.E0 = take(c, 8 * M);   // level 0: (u, v) only; id = position, rank in `rank`
     L.EA = take(c, sizeof(EdgeRec) * E1);
     L.EB = take(c, sizeof(EdgeRec) * E2);
     L.min64 = take(c, 8 * N);
@@ -560,14 +560,14 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             LevelArgs a = level_args(j);
             a.cap_m = (int32_t)m;
             a.cap_n = (int32_t)n;
-            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 28.0 : 12.0) * m + 8.0 * n,
+            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 20.0 : 12.0) * m + 8.0 * n,
                      launch_min_incident(l0, a, s));
             if (m <= persist_max) {
                 PD_TIMED(PK_LEVELS, 60.0 * m, persistent_from(j));
                 break;
             }
             PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 28.0 : 24.0) * n, launch_own(l0, a, s));
-            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 21.0 * m, launch_classify(a, s));
+            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, (l0 ? 13.0 : 21.0) * m, launch_classify(a, s));
             for (int round = 0;; ++round) {
                 if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
                 a.round = round;
