@@ -136,7 +136,7 @@ PANDORA_API int pandora_dendrogram_batched_async(int32_t B, const int64_t* voff,
  *   - No profiler events are recorded; pandora_last_stats is kept.
  */
 #define PANDORA_NOALLOC_SCRATCH_BYTES (64u << 20)
-#define PANDORA_NOALLOC_MAX_VERTICES 771073   /* largest n that fits, any tuning */
+#define PANDORA_NOALLOC_MAX_VERTICES 798594   /* largest n that fits, any tuning */
 PANDORA_API int pandora_dendrogram_noalloc(int64_t n, const int32_t* u, const int32_t* v, const float* w,
                                            int32_t* edge_parent, int32_t* vertex_parent, void* hip_stream);
 

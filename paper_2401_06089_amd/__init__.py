@@ -205,7 +205,7 @@ def dendrogram(u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
 
 # Largest tree pandora_dendrogram_noalloc accepts (its fixed scratch array).
 NOALLOC_SCRATCH_BYTES = 64 << 20
-NOALLOC_MAX_VERTICES = 771073
+NOALLOC_MAX_VERTICES = 798594
 
 
 def dendrogram_noalloc_into(n: int, u, v, w, edge_parent, vertex_parent, stream=None) -> int:

@@ -76,10 +76,13 @@ constexpr int kScanTile = kScanBlock * kScanItems;   // 2048 edges per workgroup
 
 __host__ __device__ inline int64_t scan_tiles(int64_t m) { return (m + kScanTile - 1) / kScanTile; }
 
-// One edge of a level: endpoints (level-local ids), global rank, and at level 0
-// the global input id (a 16-byte record: one cache-line touch per gather).
-struct alignas(16) EdgeRec {
-    int32_t u, v, r, id;
+// One edge of a level: its endpoints (level-local ids) in an 8-byte record,
+// and its global rank in a parallel array.  The pointer-chasing steps gather
+// only records, so a smaller record means more of them per cached line.  At
+// level 0 the rank array is the rank of every input edge, and an edge's
+// input id is its position.
+struct EdgeRec {
+    int32_t u, v, r;
 };
 
 // Per flat vertex: rank of its lightest edge at its level (kInf if none) and
@@ -107,7 +110,8 @@ struct LevelArgs {
     const int32_t* in_v;
     const int32_t* rank;       // level 0: rank of each input edge
     Forest forest;
-    EdgeRec* E;                // this level's edges (level 0: written by k_min_incident)
+    i32x2* E;                  // this level's edge records (level 0: written by k_min_incident)
+    const int32_t* Er;         // ... and their ranks (level 0: `rank`)
     uint64_t* min64;           // per vertex: (rank << 32) | position of its lightest edge
     VInfo* vinfo_all;          // flat per-vertex table of all levels
     int32_t* ptr;              // contraction pointers / final labels (kLabelFlag set)
@@ -115,7 +119,8 @@ struct LevelArgs {
     uint8_t* alpha;            // per-edge alpha flag
     uint64_t* scan_lb;         // look-back words, one per scan tile
     int32_t* tile_alpha_excl;  // alpha prefix at the start of each scan tile
-    EdgeRec* out;              // next level edges
+    i32x2* out;                // next level's edge records
+    int32_t* out_r;            // ... and their ranks
     int32_t cap_next_e;
     int32_t cap_next_v;
     int32_t* svflat;           // per rank: flat id of the supervertex the edge is contracted into
@@ -137,9 +142,11 @@ hipError_t launch_min_incident(bool level0, const LevelArgs& a, hipStream_t s);
 // all levels; the per-level fields are filled from the capacities.
 struct PersistArgs {
     LevelArgs a;
-    EdgeRec* E0;
-    EdgeRec* EA;
-    EdgeRec* EB;
+    i32x2* E0;
+    i32x2* EA;
+    i32x2* EB;
+    int32_t* EA_r;
+    int32_t* EB_r;
     int32_t first_level, last_level;
     int32_t jump_rounds;     // pointer-jumping rounds; the last is bounded only by the level size
     int32_t capE[kMaxLevels + 1];
@@ -157,8 +164,10 @@ constexpr int kTailE = 4096;
 constexpr int kTailV = 8192;
 
 struct TailArgs {
-    const EdgeRec* EA;         // level edges of odd levels
-    const EdgeRec* EB;         // level edges of even levels >= 2
+    const i32x2* EA;           // level edges of odd levels
+    const i32x2* EB;           // level edges of even levels >= 2
+    const int32_t* EA_r;       // their ranks
+    const int32_t* EB_r;
     const int32_t* in_u;       // level-0 entry: caller's endpoints and ranks
     const int32_t* in_v;
     const int32_t* rank;

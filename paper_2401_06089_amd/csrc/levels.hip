@@ -147,23 +147,16 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
         }
         e.u = (int32_t)(v0 + x);
         e.v = (int32_t)(v0 + y);
-        e.id = (int32_t)i;
-        store_stream(reinterpret_cast<i32x2*>(a.E) + i, i32x2{e.u, e.v});
+        store_stream(a.E + i, i32x2{e.u, e.v});
     } else {
-        e = a.E[i];
+        const i32x2 uv = load_stream(a.E + i);
+        e = EdgeRec{uv.x, uv.y, load_stream(a.Er + i)};
     }
     const uint64_t key = ((uint64_t)(uint32_t)e.r << 32) | (uint64_t)(uint32_t)i;
     // Read first: values only decrease, so a stale read can only cause a
     // redundant atomic, never a missed one.
     if (a.min64[e.u] > key) atomicMin((unsigned long long*)&a.min64[e.u], (unsigned long long)key);
     if (a.min64[e.v] > key) atomicMin((unsigned long long*)&a.min64[e.v], (unsigned long long)key);
-}
-
-// Level 0 keeps only the endpoints of each edge (8 bytes): its id is its
-// position and its rank sits in the rank array.  Deeper levels keep 16-byte
-// records (endpoints, rank).
-__device__ __forceinline__ const i32x2* level0_recs(const LevelArgs& a) {
-    return reinterpret_cast<const i32x2*>(a.E);
 }
 
 // ---- per-item and per-tile bodies ---------------------------------------------
@@ -189,19 +182,13 @@ __device__ __forceinline__ void own_item(const LevelArgs& a, const LevelView& L,
         raise_err(a.ctrl, kErrOverflow);
         return;
     }
-    EdgeRec e;
-    if (L0) {
-        const i32x2 uv = level0_recs(a)[pos];
-        e = EdgeRec{uv.x, uv.y, 0, (int32_t)pos};
-    } else {
-        e = a.E[pos];
-    }
-    const int side = (e.u == (int32_t)x) ? 0 : 1;
-    a.ptr[x] = side ? e.u : e.v;
+    const i32x2 e = a.E[pos];
+    const int side = (e.x == (int32_t)x) ? 0 : 1;
+    a.ptr[x] = side ? e.x : e.y;
     reinterpret_cast<uint8_t*>(a.own)[2 * (int64_t)pos + side] = 1;
     vinfo[x].minInc = (int32_t)(mm >> 32);
     if (L0) {
-        int32_t vp = e.id;
+        int32_t vp = (int32_t)pos;   // level 0: the edge's input id is its position
         if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex_fast(x)));
         store_stream(a.vertex_parent + x, vp);
     }
@@ -231,14 +218,8 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
         if (idx < L.m) {
             const uint16_t o = a.own[idx];
             a.own[idx] = 0;
-            EdgeRec e;
-            if (L0) {
-                const i32x2 uv = load_stream(level0_recs(a) + idx);
-                e = EdgeRec{uv.x, uv.y, 0, 0};
-            } else {
-                const i32x4 ev = load_stream(reinterpret_cast<const i32x4*>(a.E + idx));
-                e = EdgeRec{ev.x, ev.y, ev.z, ev.w};
-            }
+            const i32x2 uv = load_stream(a.E + idx);
+            const EdgeRec e{uv.x, uv.y, 0};
             selfloop |= e.u == e.v;
             al = o == 0;
             lf = o == 0x0101;
@@ -427,26 +408,16 @@ __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView
     for (int k = 0; k < kScanItems; ++k) {
         if (!(amask & (1u << k))) continue;
         const int64_t idx = base + k * kScanBlock + tid;
-        EdgeRec e;
-        if (L0) {
-            const i32x2 uv = load_stream(level0_recs(a) + idx);
-            e = EdgeRec{uv.x, uv.y, load_stream(a.rank + idx), (int32_t)idx};
-        } else {
-            const i32x4 ev = load_stream(reinterpret_cast<const i32x4*>(a.E + idx));
-            e = EdgeRec{ev.x, ev.y, ev.z, ev.w};
-        }
+        const i32x2 uv = load_stream(a.E + idx);
+        const EdgeRec e{uv.x, uv.y, load_stream(a.Er + idx)};
         const int32_t lx = vinfo[e.u].label;
         const int32_t ly = vinfo[e.v].label;
         const int64_t pos = abase + s_ca[k][wave] + apre[k];
         selfloop |= lx == ly;
         const int64_t ux = (int64_t)lx - L.off_next, vx = (int64_t)ly - L.off_next;
         if (pos < nx.m && ux >= 0 && ux < nx.n && vx >= 0 && vx < nx.n) {
-            EdgeRec o;
-            o.u = (int32_t)ux;
-            o.v = (int32_t)vx;
-            o.r = e.r;
-            o.id = 0;
-            store_stream(reinterpret_cast<i32x4*>(a.out + pos), i32x4{o.u, o.v, o.r, o.id});
+            store_stream(a.out + pos, i32x2{(int32_t)ux, (int32_t)vx});
+            store_stream(a.out_r + pos, e.r);
             if (BID) {
                 // the next level's lightest incident edges (its min64 words
                 // were reset by this level's pointer jumping)
@@ -611,7 +582,9 @@ __global__ __launch_bounds__(kScanBlock) void k_levels(PersistArgs p) {
         a.cap_next_e = p.capE[j + 1];
         a.cap_next_v = p.capV[j + 1];
         a.E = j == 0 ? p.E0 : (j % 2 == 1 ? p.EA : p.EB);
+        a.Er = j == 0 ? p.a.rank : (j % 2 == 1 ? p.EA_r : p.EB_r);
         a.out = j % 2 == 0 ? p.EA : p.EB;
+        a.out_r = j % 2 == 0 ? p.EA_r : p.EB_r;
         const LevelView L = level_view(a);   // written before the last barrier: the same everywhere
         if (L.skip) break;
         if (j == 0) persistent_level<true>(a, L, p.jump_rounds, bar, &s_tile);
@@ -656,7 +629,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
         ++entry;
     const LevelInfo E0 = a.ctrl->lv[entry];
     const bool level0 = entry == 0;
-    const EdgeRec* ent = (entry % 2 == 1) ? a.EA : a.EB;
+    const i32x2* ent = (entry % 2 == 1) ? a.EA : a.EB;
+    const int32_t* ent_r = (entry % 2 == 1) ? a.EA_r : a.EB_r;
     int32_t m = E0.m, n = E0.n;
     int64_t off = E0.off;
     if (!tail_level(m, n, kTailE, kTailV) || off + (m > 0 ? n : 0) > a.flat_cap) {
@@ -681,10 +655,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
             s_v[i] = (int32_t)(v0 + y);
             s_r[i] = a.rank[i];
         } else {
-            const EdgeRec e = ent[i];
-            s_u[i] = e.u;
-            s_v[i] = e.v;
-            s_r[i] = e.r;
+            const i32x2 e = ent[i];
+            s_u[i] = e.x;
+            s_v[i] = e.y;
+            s_r[i] = ent_r[i];
         }
     }
     __syncthreads();

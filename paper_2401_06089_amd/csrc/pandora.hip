@@ -109,7 +109,7 @@ struct Layout {
     int chain_bits = 8;
     int sort_cfg = kDefaultSortCfg;
     int64_t lb_words_w = 0, lb_words_c = 0;   // look-back words per pass (weight / chain sort)
-    size_t ctrl, voff, tidx, K0, K1, V0, V1, perm, rank, E0, EA, EB, min64, own, alpha, scan_lb,
+    size_t ctrl, voff, tidx, K0, K1, V0, V1, perm, rank, E0, EA, EB, EA_r, EB_r, min64, own, alpha, scan_lb,
         tile_excl, vinfo, ptr, svflat, lb0, lb1;
     size_t total = 0;
 };
@@ -183,9 +183,11 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
     L.V1 = take(c, 4 * M);
     L.perm = take(c, 4 * M);
     L.rank = take(c, 4 * M);
-    L.E0 = take(c, 8 * M);   // level 0: (u, v) only; id = position, rank in `rank`
-    L.EA = take(c, sizeof(EdgeRec) * E1);
-    L.EB = take(c, sizeof(EdgeRec) * E2);
+    L.E0 = take(c, 8 * M);   // level 0: (u, v); id = position, rank in `rank`
+    L.EA = take(c, 8 * E1);
+    L.EB = take(c, 8 * E2);
+    L.EA_r = take(c, 4 * E1);
+    L.EB_r = take(c, 4 * E2);
     L.min64 = take(c, 8 * N);
     L.own = take(c, 2 * M);
     L.alpha = take(c, M);
@@ -495,9 +497,11 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
     }
 
     // ---- 2. contraction levels --------------------------------------------------
-    EdgeRec* E0 = at<EdgeRec>(d, L.E0);
-    EdgeRec* EA = at<EdgeRec>(d, L.EA);
-    EdgeRec* EB = at<EdgeRec>(d, L.EB);
+    i32x2* E0 = at<i32x2>(d, L.E0);
+    i32x2* EA = at<i32x2>(d, L.EA);
+    i32x2* EB = at<i32x2>(d, L.EB);
+    int32_t* EA_r = at<int32_t>(d, L.EA_r);
+    int32_t* EB_r = at<int32_t>(d, L.EB_r);
     const int jump_steps = tune.jump_steps > 0 ? tune.jump_steps : 16;
     auto level_args = [&](int j) {
         LevelArgs a{};
@@ -509,7 +513,9 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         a.rank = rank;
         a.forest = forest;
         a.E = j == 0 ? E0 : (j % 2 == 1 ? EA : EB);
+        a.Er = j == 0 ? rank : (j % 2 == 1 ? EA_r : EB_r);
         a.out = j % 2 == 0 ? EA : EB;
+        a.out_r = j % 2 == 0 ? EA_r : EB_r;
         a.min64 = min64;
         a.vinfo_all = vinfo_all;
         a.ptr = at<int32_t>(d, L.ptr);
@@ -535,6 +541,8 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         p.E0 = E0;
         p.EA = EA;
         p.EB = EB;
+        p.EA_r = EA_r;
+        p.EB_r = EB_r;
         p.first_level = j;
         p.last_level = L.Lmax;
         p.jump_rounds = kPersistJumpRounds;
@@ -626,6 +634,8 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         TailArgs t{};
         t.EA = EA;
         t.EB = EB;
+        t.EA_r = EA_r;
+        t.EB_r = EB_r;
         t.in_u = u;
         t.in_v = v;
         t.rank = rank;

@@ -107,7 +107,7 @@ def test_argument_errors_come_back_before_any_launch(lib):
     assert lib.pandora_dendrogram_noalloc(10, None, d, d, d, d, None) == INVALID_ARG
     assert lib.pandora_dendrogram_noalloc(10, d, d, d, d, None, None) == INVALID_ARG
     assert lib.pandora_dendrogram_noalloc(1_200_000_000, d, d, d, d, d, None) == INVALID_ARG
-    assert lib.pandora_dendrogram_noalloc(771_074, d, d, d, d, d, None) == 4   # OUT_OF_MEMORY
+    assert lib.pandora_dendrogram_noalloc(798_595, d, d, d, d, d, None) == 4   # OUT_OF_MEMORY
     assert lib.pandora_dendrogram_noalloc(50_000_000, d, d, d, d, d, None) == 4
 
     def voff(*xs):
