@@ -113,7 +113,10 @@ struct LevelArgs {
     i32x2* E;                  // this level's edge records (level 0: written by k_min_incident)
     const int32_t* Er;         // ... and their ranks (level 0: `rank`)
     uint64_t* min64;           // per vertex: (rank << 32) | position of its lightest edge
-    VInfo* vinfo_all;          // flat per-vertex table of all levels
+    VInfo* vinfo_all;          // flat per-vertex table of all levels (level 0 as min0, lab0)
+    int32_t* min0;             // level 0: lightest incident rank of each vertex
+    int32_t* lab0;             // level 0: flat id of each vertex's supervertex
+                               // (both in level 0's part of vinfo_all)
     int32_t* ptr;              // contraction pointers / final labels (kLabelFlag set)
     uint16_t* own;             // per edge: byte 0 = owned by u, byte 1 = owned by v
     uint8_t* alpha;            // per-edge alpha flag

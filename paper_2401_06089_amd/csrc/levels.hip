@@ -173,7 +173,8 @@ __device__ __forceinline__ void own_item(const LevelArgs& a, const LevelView& L,
     if (b != 0 && lane_id() == __ffsll((long long)b) - 1) atomicAdd(&a.ctrl->isolated, (uint32_t)popc64(b));
     if (!live) return;
     if (isolated) {
-        vinfo[x].minInc = kInf;
+        if (L0) a.min0[x] = kInf;
+        else vinfo[x].minInc = kInf;
         if (L0) a.vertex_parent[x] = -1;
         return;
     }
@@ -186,7 +187,8 @@ __device__ __forceinline__ void own_item(const LevelArgs& a, const LevelView& L,
     const int side = (e.x == (int32_t)x) ? 0 : 1;
     a.ptr[x] = side ? e.x : e.y;
     reinterpret_cast<uint8_t*>(a.own)[2 * (int64_t)pos + side] = 1;
-    vinfo[x].minInc = (int32_t)(mm >> 32);
+    if (L0) a.min0[x] = (int32_t)(mm >> 32);
+    else vinfo[x].minInc = (int32_t)(mm >> 32);
     if (L0) {
         int32_t vp = (int32_t)pos;   // level 0: the edge's input id is its position
         if (a.forest.B > 1) vp = (int32_t)(vp - a.forest.edge_base(a.forest.tree_of_vertex_fast(x)));
@@ -295,9 +297,17 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
 }
 
 // One vertex x < L.n, one pointer-jumping round of at most `steps` steps.
+// Level 0 keeps its minima and labels in two plain arrays (no expansion walk
+// reads them, and the compaction's label gathers then find twice as many
+// labels per cached line); deeper levels in the flat records.
+template <bool L0>
 __device__ __forceinline__ void jump_item(const LevelArgs& a, const LevelView& L, int64_t x, int round,
                                           int steps) {
     VInfo* vinfo = a.vinfo_all + L.off;
+    auto set_label = [&](int32_t lab) {
+        if (L0) a.lab0[x] = lab;
+        else vinfo[x].label = lab;
+    };
     // After the first round a labelled pointer means the vertex was finished
     // in an earlier round (label and supervertex record already written); an
     // isolated vertex returns below either way.
@@ -307,9 +317,9 @@ __device__ __forceinline__ void jump_item(const LevelArgs& a, const LevelView& L
         if (nn > a.cap_next_v) nn = a.cap_next_v;
         if (x < nn) store_stream(a.min64 + x, kNoEdge);     // the next level starts clean
     }
-    const int32_t r = load_stream(&vinfo[x].minInc);
+    const int32_t r = L0 ? load_stream(a.min0 + x) : load_stream(&vinfo[x].minInc);
     if (r == kInf) {
-        if (round == 0) vinfo[x].label = -1;
+        if (round == 0) set_label(-1);
         return;
     }
     int32_t q = a.ptr[x];
@@ -339,7 +349,7 @@ __device__ __forceinline__ void jump_item(const LevelArgs& a, const LevelView& L
         a.ptr[x] = t;                            // x now holds its label directly
     }
     const int32_t flat = (int32_t)(L.off_next + lab);
-    vinfo[x].label = flat;
+    set_label(flat);
     if (leaf_root) a.svflat[r] = flat | kLabelFlag;
     else if (!leaf_end) a.svflat[r] = flat;      // the lightest edge of x falls into this supervertex
 }
@@ -410,8 +420,8 @@ __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView
         const int64_t idx = base + k * kScanBlock + tid;
         const i32x2 uv = load_stream(a.E + idx);
         const EdgeRec e{uv.x, uv.y, load_stream(a.Er + idx)};
-        const int32_t lx = vinfo[e.u].label;
-        const int32_t ly = vinfo[e.v].label;
+        const int32_t lx = L0 ? a.lab0[e.u] : vinfo[e.u].label;
+        const int32_t ly = L0 ? a.lab0[e.v] : vinfo[e.v].label;
         const int64_t pos = abase + s_ca[k][wave] + apre[k];
         selfloop |= lx == ly;
         const int64_t ux = (int64_t)lx - L.off_next, vx = (int64_t)ly - L.off_next;
@@ -469,7 +479,7 @@ __global__ __launch_bounds__(256) void k_jump(LevelArgs a) {
     if (a.ctrl->err) return;                     // invalid input: outputs are unspecified
     const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (x >= L.n) return;
-    jump_item(a, L, x, a.round, a.jump_steps);
+    jump_item<L0>(a, L, x, a.round, a.jump_steps);
 }
 
 template <bool L0>
@@ -548,7 +558,7 @@ __device__ void persistent_level(const LevelArgs& a, const LevelView& L, int jum
         // the bit of the next round is not read or written during this one
         if (gtid == 0) atomicAnd(&c->not_converged, ~(1u << ((round + 1) & 31)));
         if (!err_set(c))
-            for (int64_t x = gtid; x < L.n; x += gsize) jump_item(a, L, x, round, steps);
+            for (int64_t x = gtid; x < L.n; x += gsize) jump_item<L0>(a, L, x, round, steps);
         grid_barrier(c, bar);
         const uint32_t nc = __hip_atomic_load(&c->not_converged, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!(nc & (1u << (round & 31)))) break;

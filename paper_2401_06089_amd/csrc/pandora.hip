@@ -518,6 +518,10 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         a.out_r = j % 2 == 0 ? EA_r : EB_r;
         a.min64 = min64;
         a.vinfo_all = vinfo_all;
+        // level 0's minima and labels live in its part of the flat table
+        // (2 x 4 bytes per vertex), as two plain arrays
+        a.min0 = reinterpret_cast<int32_t*>(vinfo_all);
+        a.lab0 = a.min0 + N;
         a.ptr = at<int32_t>(d, L.ptr);
         a.own = own;
         a.alpha = at<uint8_t>(d, L.alpha);
