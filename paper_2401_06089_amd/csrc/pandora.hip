@@ -572,18 +572,18 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             LevelArgs a = level_args(j);
             a.cap_m = (int32_t)m;
             a.cap_n = (int32_t)n;
-            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 20.0 : 12.0) * m + 8.0 * n,
+            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 20.0 : 12.0) * m + 16.0 * n,
                      launch_min_incident(l0, a, s));
             if (m <= persist_max) {
                 PD_TIMED(PK_LEVELS, 60.0 * m, persistent_from(j));
                 break;
             }
-            PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 28.0 : 24.0) * n, launch_own(l0, a, s));
-            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, (l0 ? 13.0 : 21.0) * m, launch_classify(a, s));
+            PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 29.0 : 25.0) * n, launch_own(l0, a, s));
+            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 11.0 * m, launch_classify(a, s));
             for (int round = 0;; ++round) {
                 if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
                 a.round = round;
-                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 24.0 : 16.0) * n, launch_jump(a, s));
+                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 28.0 : 16.0) * n, launch_jump(a, s));
                 ++st.jump_launches;
                 rc = read_ctrl(ctrl, hctrl, s);
                 if (rc != PANDORA_OK) return rc;
@@ -593,7 +593,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
             if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
                 return PANDORA_ERR_NOT_A_TREE;
-            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 40.0 * m_next, launch_compact(a, s));
+            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 32.0 * m_next, launch_compact(a, s));
             off += n;
             n = n_next;
             m = m_next;
@@ -616,20 +616,22 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             const bool l0 = j == 0;
             LevelArgs a = level_args(j);
             const double mj = (double)L.capE[j], nj = (double)L.capV[j];
-            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, 12.0 * mj, launch_min_incident(l0, a, s));
+            PD_TIMED(l0 ? PK_MIN_INC : PK_MIN_INC_N, (l0 ? 20.0 : 12.0) * mj + 16.0 * nj,
+                     launch_min_incident(l0, a, s));
             if (L.capE[j] <= persist_max) {
                 PD_TIMED(PK_LEVELS, 60.0 * mj, persistent_from(j));
                 break;
             }
-            PD_TIMED(l0 ? PK_OWN : PK_OWN_N, 24.0 * nj, launch_own(l0, a, s));
-            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 21.0 * mj, launch_classify(a, s));
+            PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 29.0 : 25.0) * nj, launch_own(l0, a, s));
+            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 11.0 * mj, launch_classify(a, s));
             for (int round = 0; round < kSyncFreeJumpRounds; ++round) {
                 a.round = round;
                 a.jump_steps = round + 1 < kSyncFreeJumpRounds ? jump_steps : (int)std::max<int64_t>(L.capV[j], 16);
-                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, 24.0 * nj, launch_jump(a, s));
+                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 28.0 : 16.0) * nj, launch_jump(a, s));
                 ++st.jump_launches;
             }
-            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 14.0 * mj, launch_compact(a, s));
+            // sizes are capacities here; about a third of a level's edges are alpha
+            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, (1.0 + 32.0 / 3.0) * mj, launch_compact(a, s));
         }
     }
 
@@ -669,7 +671,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         const int64_t lbw_c = sort_tiles(M, L.sort_cfg) << chain_bits;
         wa.lb_zero_words = lbw_c;
         wa.ctrl = ctrl;
-        PD_TIMED(PK_WALK_HIST, 12.0 * M, launch_walk_hist(wa, s));
+        PD_TIMED(PK_WALK_HIST, 16.0 * M, launch_walk_hist(wa, s));
         const uint32_t* kin = K[0];
         const int32_t* vin = perm;
         st.chain_passes = chain_passes;
