@@ -75,6 +75,11 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;   // 2048 edges per workgroup
 
 __host__ __device__ inline int64_t scan_tiles(int64_t m) { return (m + kScanTile - 1) / kScanTile; }
+// The classification scans tiles of two compaction tiles each (it records
+// the alpha prefix at the start of both halves).
+constexpr int kClsItems = 2 * kScanItems;
+constexpr int kClsTile = kScanBlock * kClsItems;     // 4096 edges per workgroup
+__host__ __device__ inline int64_t cls_tiles(int64_t m) { return (m + kClsTile - 1) / kClsTile; }
 
 // One edge of a level: its endpoints (level-local ids) in an 8-byte record,
 // and its global rank in a parallel array.  The pointer-chasing steps gather

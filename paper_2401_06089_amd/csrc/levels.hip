@@ -196,23 +196,24 @@ __device__ __forceinline__ void own_item(const LevelArgs& a, const LevelView& L,
     }
 }
 
-// One claimed scan tile of the alpha/leaf classification (whole workgroup).
+// One claimed tile of the alpha/leaf classification (whole workgroup): the
+// edges of two consecutive compaction tiles.
 template <bool L0>
 __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelView& L, int64_t tile) {
     constexpr int W = kScanBlock / kWave;
-    __shared__ uint32_t s_ca[kScanItems][W];
-    __shared__ uint32_t s_cl[kScanItems][W];
+    static_assert(kClsItems * W == kWave, "one (item, wave) count per lane of the prefix wave");
+    __shared__ uint32_t s_cnt[kClsItems][W];   // alpha count << 16 | leaf count, then their prefix
     __shared__ uint64_t s_excl;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    const int64_t base = tile * kScanTile;
+    const int64_t base = tile * kClsTile;
     const uint64_t lt = lanemask_lt();
 
     uint32_t lmask = 0;
-    uint32_t lpre[kScanItems];
-    int32_t root[kScanItems], other[kScanItems];
+    uint32_t lpre[kClsItems];
+    int32_t root[kClsItems], other[kClsItems];
     bool selfloop = false;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < kClsItems; ++k) {
         const int64_t idx = base + k * kScanBlock + tid;
         bool al = false, lf = false;
         root[k] = 0;
@@ -233,36 +234,31 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
         const uint64_t bl = ballot(lf);
         lpre[k] = (uint32_t)popc64(bl & lt);
         lmask |= (lf ? 1u : 0u) << k;
-        if (lane == 0) {
-            s_ca[k][wave] = (uint32_t)popc64(ba);
-            s_cl[k][wave] = (uint32_t)popc64(bl);
-        }
+        if (lane == 0) s_cnt[k][wave] = ((uint32_t)popc64(ba) << 16) | (uint32_t)popc64(bl);
     }
     if (ballot(selfloop) != 0 && lane == 0) raise_err(a.ctrl, kErrNotTree);
     __syncthreads();
     if (wave == 0) {
-        uint64_t agg = 0;
-        if (lane == 0) {
-            uint32_t sa = 0, sl = 0;
-            for (int k = 0; k < kScanItems; ++k)
-                for (int w = 0; w < W; ++w) {
-                    const uint32_t ca = s_ca[k][w], cl = s_cl[k][w];
-                    s_ca[k][w] = sa;
-                    s_cl[k][w] = sl;
-                    sa += ca;
-                    sl += cl;
-                }
-            agg = ((uint64_t)sa << 31) | (uint64_t)sl;
-            st_relaxed(a.scan_lb + tile, (tile == 0 ? kFlagInc : kFlagAgg) | agg);
-        }
+        // Prefix of the (item, wave) counts in edge order, one per lane (both
+        // counts are at most 4096, so they add as one word).
+        const int k = lane / W, w = lane % W;
+        const uint32_t c = s_cnt[k][w];
+        const uint32_t inc = wave_incl_scan(c);
+        s_cnt[k][w] = inc - c;
+        const uint32_t all = __shfl(inc, kWave - 1, kWave);
+        const uint32_t half = __shfl(inc - c, kScanItems * W, kWave);   // before the second half
+        const uint64_t agg = ((uint64_t)(all >> 16) << 31) | (uint64_t)(all & 0xffffu);
+        if (lane == 0) st_relaxed(a.scan_lb + tile, (tile == 0 ? kFlagInc : kFlagAgg) | agg);
         const uint64_t excl = tile > 0 ? wave_lookback(a.scan_lb, tile, a.ctrl) : 0;
         if (lane == 0) {
             if (tile > 0) st_relaxed(a.scan_lb + tile, kFlagInc | (excl + agg));
             s_excl = excl;
-            a.tile_alpha_excl[tile] = (int32_t)(excl >> 31);
-            if (tile == scan_tiles(L.m) - 1) {
-                const uint64_t all = excl + agg;
-                int32_t mn = (int32_t)(all >> 31), nn = (int32_t)(all & kLow31);
+            const int32_t ea = (int32_t)(excl >> 31);
+            a.tile_alpha_excl[2 * tile] = ea;
+            if (2 * tile + 1 < scan_tiles(L.m)) a.tile_alpha_excl[2 * tile + 1] = ea + (int32_t)(half >> 16);
+            if (tile == cls_tiles(L.m) - 1) {
+                const uint64_t tot = excl + agg;
+                int32_t mn = (int32_t)(tot >> 31), nn = (int32_t)(tot & kLow31);
                 a.ctrl->m_next = mn;
                 a.ctrl->n_next = nn;
                 // Section 4.2 bounds the next level; a larger one is not a tree.
@@ -286,9 +282,9 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
     // (the larger one marked as such), so pointer jumping stops at either.
     const int64_t leaf_base = (int64_t)(s_excl & kLow31);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < kClsItems; ++k) {
         if (lmask & (1u << k)) {
-            const int64_t pos = leaf_base + s_cl[k][wave] + lpre[k];
+            const int64_t pos = leaf_base + (s_cnt[k][wave] & 0xffffu) + lpre[k];
             const int32_t word = kLabelFlag | (int32_t)pos;
             a.ptr[root[k]] = word;
             a.ptr[other[k]] = word | kOtherEnd;
@@ -466,7 +462,7 @@ __global__ __launch_bounds__(kScanBlock) void k_classify(LevelArgs a) {
     if (threadIdx.x == 0) s_tile = atomicAdd(&a.ctrl->alpha_tiles, 1u);
     __syncthreads();
     const int64_t tile = s_tile;
-    if (tile >= scan_tiles(L.m)) return;       // surplus workgroup of a capacity-sized grid
+    if (tile >= cls_tiles(L.m)) return;        // surplus workgroup of a capacity-sized grid
     classify_tile<L0>(a, L, tile);
 }
 
@@ -546,7 +542,7 @@ __device__ void persistent_level(const LevelArgs& a, const LevelView& L, int jum
         if (tid == 0) *s_tile = err_set(c) ? 0xffffffffu : atomicAdd(&c->alpha_tiles, 1u);
         __syncthreads();
         const uint32_t t = *s_tile;
-        if (t >= (uint32_t)scan_tiles(L.m)) break;
+        if (t >= (uint32_t)cls_tiles(L.m)) break;
         classify_tile<L0>(a, L, t);
     }
     grid_barrier(c, bar);
@@ -847,8 +843,8 @@ hipError_t launch_own(bool level0, const LevelArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_classify(const LevelArgs& a, hipStream_t s) {
-    if (a.level == 0) k_classify<true><<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
-    else k_classify<false><<<blocks_for(scan_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
+    if (a.level == 0) k_classify<true><<<blocks_for(cls_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
+    else k_classify<false><<<blocks_for(cls_tiles(a.cap_m), 1), kScanBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
