@@ -137,7 +137,17 @@ struct LevelArgs {
     Control* ctrl;
     int jump_steps;
     int round;
+    int spread;                // k_min_incident visits edge blocks in a strided order (below)
 };
+
+// Level 0 of a forest of many small trees: the workgroups that run at once
+// would all work near the start of the same few trees, whose first vertices
+// collect most of the early edges' minima updates.  With `spread` set, the
+// workgroups take the edge blocks in an order strided by kSpreadGroups, so
+// that concurrent workgroups work in about kSpreadGroups places of the edge
+// list.
+constexpr int kSpreadGroups = 1024;
+constexpr int64_t kSpreadMaxMeanEdges = 1 << 16;   // spread when M <= B * this
 
 __host__ __device__ inline bool tail_level(int64_t m, int64_t n, int tail_e, int tail_v) {
     return m == 0 || (m <= tail_e && n <= tail_v);

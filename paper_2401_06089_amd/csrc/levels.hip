@@ -117,11 +117,20 @@ __device__ uint64_t wave_lookback(const uint64_t* lb, int64_t tile, Control* ctr
 
 // After an input error every level kernel returns at once: the call's outputs
 // are unspecified then, and nothing may index with the damaged tables.
+// Workgroup b of G goes to group b % K; group x takes a contiguous run of the
+// block ids (a permutation of [0, G)).
+template <int K>
+__device__ __forceinline__ int64_t spread_block(uint32_t b, uint32_t G) {
+    const uint32_t q = G / K, r = G % K, x = b % K;
+    return (int64_t)x * q + (x < r ? x : r) + b / K;
+}
+
 template <bool L0>
 __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
     const LevelView L = level_view(a);
     if (L.skip || a.ctrl->err) return;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t blk = a.spread ? spread_block<kSpreadGroups>(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t i = blk * 256 + threadIdx.x;
     if (i < scan_tiles(L.m)) a.scan_lb[i] = 0;
     if (i == 0) {
         a.ctrl->alpha_tiles = 0;

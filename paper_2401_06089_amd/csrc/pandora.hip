@@ -533,6 +533,9 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         a.vertex_parent = vertex_parent;
         a.ctrl = ctrl;
         a.jump_steps = jump_steps;
+        // measured on 4,096 trees of lognormal sizes: level 0's minima 1.88 -> 1.30 ms;
+        // forests of a few large trees are a little faster without
+        a.spread = j == 0 && B > 1 && M <= (int64_t)B * kSpreadMaxMeanEdges;
         return a;
     };
     // Levels of at most persist_max_edges edges run in one persistent launch
