@@ -29,8 +29,6 @@ constexpr int kWalkBlock = 1024;   // threads of a walk workgroup
 
 __global__ __launch_bounds__(kWalkBlock) void k_walk_hist(WalkArgs a) {
     __shared__ uint32_t s_h[4][kMaxRadix];
-    const int radix = 1 << a.bits;
-    const uint32_t mask = (uint32_t)radix - 1u;
     for (int i = threadIdx.x; i < 4 * kMaxRadix; i += blockDim.x) (&s_h[0][0])[i] = 0;
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -53,14 +51,15 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_hist(WalkArgs a) {
         }
         const uint32_t key = (uint32_t)(x - a.n0);
         a.ckey[r] = key;
-        for (int p = 0; p < a.passes; ++p) atomicAdd(&s_h[p][(key >> (a.bits * p)) & mask], 1u);
+        for (int p = 0, shift = 0; p < a.passes; shift += a.bits[p], ++p)
+            atomicAdd(&s_h[p][(key >> shift) & ((1u << a.bits[p]) - 1u)], 1u);
     }
     for (int64_t i = t0; i < a.lb_zero_words; i += stride) a.lb_zero[i] = 0;
     if (ballot(bad) != 0 && lane_id() == 0) raise_err(a.ctrl, kErrWalk);
     __syncthreads();
-    for (int i = threadIdx.x; i < a.passes * radix; i += blockDim.x) {
-        const uint32_t c = s_h[i / radix][i % radix];
-        if (c) atomicAdd(&a.ctrl->hist[a.hist_row + i / radix][i % radix], c);
+    for (int i = threadIdx.x; i < a.passes * kMaxRadix; i += blockDim.x) {
+        const uint32_t c = s_h[i / kMaxRadix][i % kMaxRadix];
+        if (c) atomicAdd(&a.ctrl->hist[a.hist_row + i / kMaxRadix][i % kMaxRadix], c);
     }
 }
 

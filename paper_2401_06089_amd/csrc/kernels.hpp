@@ -140,9 +140,10 @@ struct LevelArgs {
     int spread;                // k_min_incident visits edge blocks in a strided order (below)
 };
 
-// Level 0 of a forest of many small trees: the workgroups that run at once
-// would all work near the start of the same few trees, whose first vertices
-// collect most of the early edges' minima updates.  With `spread` set, the
+// A forest of many small trees: the workgroups that run at once would all
+// work near the start of the same few trees, whose first vertices collect
+// most of the early edges' minima updates (at every level: each level keeps
+// the trees' edges and vertices together).  With `spread` set, the
 // workgroups take the edge blocks in an order strided by kSpreadGroups, so
 // that concurrent workgroups work in about kSpreadGroups places of the edge
 // list.
@@ -208,7 +209,7 @@ struct WalkArgs {
     const int32_t* svflat;
     const VInfo* vinfo_all;
     uint32_t* ckey;            // out: chain key per rank
-    int bits;                  // digit width of the chain sort
+    int bits[4];               // digit width of each chain-sort pass, least significant first
     int hist_row;
     int passes;
     uint64_t* lb_zero;

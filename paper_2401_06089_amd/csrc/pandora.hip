@@ -99,14 +99,24 @@ int cu_count(int dev) {
     return cus;
 }
 
+// Digit widths of the chain sort's passes (least significant first).
+struct ChainDigits {
+    int passes = 1;
+    int bits[4] = {8, 8, 8, 8};
+    int widest() const {
+        int w = 0;
+        for (int p = 0; p < passes; ++p) w = std::max(w, bits[p]);
+        return w;
+    }
+};
+
 struct Layout {
     int64_t N = 0, M = 0;
     int32_t B = 0;
     int Lmax = 0;
     std::vector<int64_t> capE, capV;
     int64_t flat_cap = 0;
-    int chain_passes = 0;
-    int chain_bits = 8;
+    ChainDigits chain;
     int sort_cfg = kDefaultSortCfg;
     int64_t lb_words_w = 0, lb_words_c = 0;   // look-back words per pass (weight / chain sort)
     size_t ctrl, voff, tidx, K0, K1, V0, V1, perm, rank, E0, EA, EB, EA_r, EB_r, min64, own, alpha, scan_lb,
@@ -126,20 +136,23 @@ int ceil_log2(int64_t x) {   // smallest L with 2^L >= x (x >= 1)
     return L;
 }
 
-// Digit width and pass count of the chain sort for chain keys in
-// [0, key_range): as few passes of 9-bit digits as cover them, with 8-bit
-// digits whenever those need no more passes (or the width the tuning fixes).
-void chain_digits(int64_t key_range, int pref, int* bits_out, int* passes_out) {
-    int bits = 0;
-    while ((int64_t(1) << bits) < std::max<int64_t>(key_range, 1)) ++bits;
+// Digit widths of the chain sort for chain keys in [0, key_range): as few
+// passes as cover the keys, each of 8 bits, or of 9 bits where 8-bit passes
+// alone would need one more (a 9-bit pass is slower); or all of the width the
+// tuning fixes.  Widths are listed least significant digit first.
+ChainDigits chain_digits(int64_t key_range, int pref) {
+    int total = 0;
+    while ((int64_t(1) << total) < std::max<int64_t>(key_range, 1)) ++total;
+    ChainDigits c;
     if (pref == 8 || pref == 9) {
-        *bits_out = pref;
-        *passes_out = std::max(1, (bits + pref - 1) / pref);
-        return;
+        c.passes = std::max(1, (total + pref - 1) / pref);
+        for (int p = 0; p < c.passes; ++p) c.bits[p] = pref;
+        return c;
     }
-    const int p8 = std::max(1, (bits + 7) / 8), p9 = std::max(1, (bits + 8) / 9);
-    *bits_out = p9 < p8 ? 9 : 8;
-    *passes_out = p9 < p8 ? p9 : p8;
+    c.passes = std::max(1, (total + 8) / 9);             // fewest passes of at most 9 bits
+    const int nine = std::max(0, total - 8 * c.passes);  // 9-bit passes those need
+    for (int p = 0; p < c.passes; ++p) c.bits[p] = p < nine ? 9 : 8;
+    return c;
 }
 
 Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg = kDefaultSortCfg) {
@@ -162,7 +175,7 @@ Layout make_layout(int64_t N, int32_t B, int chain_bits_pref = 0, int sort_cfg =
     }
     L.flat_cap = 0;
     for (int64_t c : L.capV) L.flat_cap += c;
-    chain_digits(L.flat_cap - N, chain_bits_pref, &L.chain_bits, &L.chain_passes);
+    L.chain = chain_digits(L.flat_cap - N, chain_bits_pref);
 
     const int64_t E1 = std::max<int64_t>(L.capE[1], 1), E2 = std::max<int64_t>(L.capE[2], 1);
     L.sort_cfg = sort_cfg;
@@ -533,9 +546,10 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         a.vertex_parent = vertex_parent;
         a.ctrl = ctrl;
         a.jump_steps = jump_steps;
-        // measured on 4,096 trees of lognormal sizes: level 0's minima 1.88 -> 1.30 ms;
-        // forests of a few large trees are a little faster without
-        a.spread = j == 0 && B > 1 && M <= (int64_t)B * kSpreadMaxMeanEdges;
+        // measured on 4,096 trees of lognormal sizes: level 0's minima 1.88 -> 1.28 ms,
+        // the deeper levels' 0.93 -> 0.75 ms; forests of a few large trees are a little
+        // faster without
+        a.spread = B > 1 && M <= (int64_t)B * kSpreadMaxMeanEdges;
         return a;
     };
     // Levels of at most persist_max_edges edges run in one persistent launch
@@ -564,7 +578,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
     };
     const int64_t persist_max = tune.persist_max_edges;
     st.sync_free = sync_free ? 1 : 0;
-    int chain_bits = L.chain_bits, chain_passes = L.chain_passes;
+    ChainDigits chain = L.chain;
     if (!sync_free) {
         // Host-driven: exact grids, pointer jumping relaunched until it converges.
         int64_t m = M, n = N, off = 0;
@@ -609,7 +623,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         // capacity-based one, and the chain sort may need fewer or narrower
         // digits.
         const int64_t bound = std::max<int64_t>(off - N, 0) + 2 * (n + B) + 66;
-        if (bound < L.flat_cap - N) chain_digits(bound, tune.chain_digit_bits, &chain_bits, &chain_passes);
+        if (bound < L.flat_cap - N) chain = chain_digits(bound, tune.chain_digit_bits);
     } else {
         // Sync-free: every level that could exceed the LDS tail is launched with
         // capacity-sized grids; levels that turn out small or empty return at
@@ -666,24 +680,24 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         wa.flat_cap = L.flat_cap;
         wa.svflat = svflat;
         wa.vinfo_all = vinfo_all;
-        wa.bits = chain_bits;
+        for (int p = 0; p < 4; ++p) wa.bits[p] = chain.bits[p];
         wa.ckey = K[0];
         wa.hist_row = 4;
-        wa.passes = chain_passes;
+        wa.passes = chain.passes;
         wa.lb_zero = LB[0];
-        const int64_t lbw_c = sort_tiles(M, L.sort_cfg) << chain_bits;
+        const int64_t lbw_c = sort_tiles(M, L.sort_cfg) << chain.widest();
         wa.lb_zero_words = lbw_c;
         wa.ctrl = ctrl;
         PD_TIMED(PK_WALK_HIST, 16.0 * M, launch_walk_hist(wa, s));
         const uint32_t* kin = K[0];
         const int32_t* vin = perm;
-        st.chain_passes = chain_passes;
-        for (int p = 0; p < chain_passes; ++p) {
+        st.chain_passes = chain.passes;
+        for (int p = 0, shift = 0; p < chain.passes; shift += chain.bits[p], ++p) {
             SortPassArgs a{};
             a.n = M;
             a.cfg = L.sort_cfg;
-            a.bits = chain_bits;
-            a.shift = chain_bits * p;
+            a.bits = chain.bits[p];
+            a.shift = shift;
             a.pass = 4 + p;
             a.keys_in = kin;
             a.vals_in = vin;
