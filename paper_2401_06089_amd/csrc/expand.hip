@@ -45,9 +45,12 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_hist(WalkArgs a) {
                 break;
             }
             if (sv & kLabelFlag) break;
-            const VInfo vi = a.vinfo_all[x];
-            if (r < (int64_t)vi.minInc) break;
-            x = vi.label;
+            // one 8-byte load: both fields arrive together (separate loads
+            // would fetch the label only after the comparison, a second
+            // dependent trip per step)
+            const i32x2 vi = *reinterpret_cast<const i32x2*>(a.vinfo_all + x);
+            if (r < (int64_t)vi.x) break;
+            x = vi.y;
         }
         const uint32_t key = (uint32_t)(x - a.n0);
         a.ckey[r] = key;
