@@ -69,12 +69,19 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_hist(WalkArgs a) {
 __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= a.m) return;
-    const uint32_t c = a.skey[i];
-    const int32_t id = a.sid[i];
+    // The four sequential loads go out together: waiting for each before the
+    // next (as the branches below would otherwise order them) costs a memory
+    // round trip apiece.
+    const bool has_next = i + 1 < a.m;
+    uint32_t c = a.skey[i];
+    int32_t id = a.sid[i];
+    uint32_t c_next = has_next ? a.skey[i + 1] : 0u;
+    int32_t id_next = has_next ? a.sid[i + 1] : -1;
+    asm volatile("" : "+v"(c), "+v"(id), "+v"(c_next), "+v"(id_next));
     if (id < 0 || id >= a.m || (int64_t)c >= a.flat_cap - a.n0) return;   // only after a reported error
     int32_t parent;
-    if (i + 1 < a.m && a.skey[i + 1] == c) {
-        parent = a.sid[i + 1];
+    if (has_next && c_next == c) {
+        parent = id_next;
     } else {
         const int32_t p = a.vinfo_all[a.n0 + (int64_t)c].minInc;
         parent = (p < 0 || p >= a.m) ? -1 : a.perm[p];

@@ -163,9 +163,11 @@ __global__ __launch_bounds__(256) void k_min_incident(LevelArgs a) {
     }
     const uint64_t key = ((uint64_t)(uint32_t)e.r << 32) | (uint64_t)(uint32_t)i;
     // Read first: values only decrease, so a stale read can only cause a
-    // redundant atomic, never a missed one.
-    if (a.min64[e.u] > key) atomicMin((unsigned long long*)&a.min64[e.u], (unsigned long long)key);
-    if (a.min64[e.v] > key) atomicMin((unsigned long long*)&a.min64[e.v], (unsigned long long)key);
+    // redundant atomic, never a missed one.  Both reads go out together.
+    uint64_t mu = a.min64[e.u], mv = a.min64[e.v];
+    asm volatile("" : "+v"(mu), "+v"(mv));
+    if (mu > key) atomicMin((unsigned long long*)&a.min64[e.u], (unsigned long long)key);
+    if (mv > key) atomicMin((unsigned long long*)&a.min64[e.v], (unsigned long long)key);
 }
 
 // ---- per-item and per-tile bodies ---------------------------------------------
@@ -221,6 +223,17 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
     uint32_t lpre[kClsItems];
     int32_t root[kClsItems], other[kClsItems];
     bool selfloop = false;
+    // All of the thread's loads go out before any is used (past the end the
+    // last edge is read instead).
+    uint32_t ov[kClsItems];
+    i32x2 ev[kClsItems];
+#pragma unroll
+    for (int k = 0; k < kClsItems; ++k) {
+        int64_t idx = base + k * kScanBlock + tid;
+        idx = idx < L.m ? idx : L.m - 1;
+        ov[k] = a.own[idx];
+        ev[k] = load_stream(a.E + idx);
+    }
 #pragma unroll
     for (int k = 0; k < kClsItems; ++k) {
         const int64_t idx = base + k * kScanBlock + tid;
@@ -228,10 +241,9 @@ __device__ __forceinline__ void classify_tile(const LevelArgs& a, const LevelVie
         root[k] = 0;
         other[k] = 0;
         if (idx < L.m) {
-            const uint16_t o = a.own[idx];
+            const uint32_t o = ov[k];
             a.own[idx] = 0;
-            const i32x2 uv = load_stream(a.E + idx);
-            const EdgeRec e{uv.x, uv.y, 0};
+            const EdgeRec e{ev[k].x, ev[k].y, 0};
             selfloop |= e.u == e.v;
             al = o == 0;
             lf = o == 0x0101;
@@ -322,12 +334,16 @@ __device__ __forceinline__ void jump_item(const LevelArgs& a, const LevelView& L
         if (nn > a.cap_next_v) nn = a.cap_next_v;
         if (x < nn) store_stream(a.min64 + x, kNoEdge);     // the next level starts clean
     }
+    // both loads go out together (the pointer is not needed for an isolated
+    // vertex, which is rare, but waiting for the minimum first would put a
+    // second memory round trip in front of every chase)
     const int32_t r = L0 ? load_stream(a.min0 + x) : load_stream(&vinfo[x].minInc);
+    int32_t q = a.ptr[x];
+    asm volatile("" : "+v"(q));   // keeps the load here, ahead of the branch below
     if (r == kInf) {
         if (round == 0) set_label(-1);
         return;
     }
-    int32_t q = a.ptr[x];
     int32_t lab;
     // In the first round only the two endpoints of a leaf edge start with a
     // label (the classification wrote it), and their lightest edge is that
@@ -395,12 +411,26 @@ __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView
     const VInfo* vinfo = a.vinfo_all + L.off;
     const int64_t base = tile * kScanTile;
     const uint64_t lt = lanemask_lt();
+    // All of the thread's loads go out before any is used: the alpha flags,
+    // and the records and ranks (their lines come in whole anyway, for the
+    // alpha edges among them).  Past the end the last edge is read instead.
+    uint32_t alv[kScanItems];
+    i32x2 uv[kScanItems];
+    int32_t rk[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + k * kScanBlock + tid;
+        idx = idx < L.m ? idx : L.m - 1;
+        alv[k] = load_stream(a.alpha + idx);
+        uv[k] = load_stream(a.E + idx);
+        rk[k] = load_stream(a.Er + idx);
+    }
     uint32_t amask = 0;
     uint32_t apre[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t idx = base + k * kScanBlock + tid;
-        const bool al = idx < L.m && load_stream(a.alpha + idx) != 0;
+        const bool al = idx < L.m && alv[k] != 0;
         const uint64_t ba = ballot(al);
         apre[k] = (uint32_t)popc64(ba & lt);
         amask |= (al ? 1u : 0u) << k;
@@ -418,25 +448,31 @@ __device__ __forceinline__ void compact_tile(const LevelArgs& a, const LevelView
     }
     __syncthreads();
     const int64_t abase = a.tile_alpha_excl[tile];
+    // the endpoints' labels, all requested before any is used
+    int32_t lx[kScanItems], ly[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        lx[k] = 0;
+        ly[k] = 0;
+        if (amask & (1u << k)) {
+            lx[k] = L0 ? a.lab0[uv[k].x] : vinfo[uv[k].x].label;
+            ly[k] = L0 ? a.lab0[uv[k].y] : vinfo[uv[k].y].label;
+        }
+    }
     bool selfloop = false, overflow = false;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (!(amask & (1u << k))) continue;
-        const int64_t idx = base + k * kScanBlock + tid;
-        const i32x2 uv = load_stream(a.E + idx);
-        const EdgeRec e{uv.x, uv.y, load_stream(a.Er + idx)};
-        const int32_t lx = L0 ? a.lab0[e.u] : vinfo[e.u].label;
-        const int32_t ly = L0 ? a.lab0[e.v] : vinfo[e.v].label;
         const int64_t pos = abase + s_ca[k][wave] + apre[k];
-        selfloop |= lx == ly;
-        const int64_t ux = (int64_t)lx - L.off_next, vx = (int64_t)ly - L.off_next;
+        selfloop |= lx[k] == ly[k];
+        const int64_t ux = (int64_t)lx[k] - L.off_next, vx = (int64_t)ly[k] - L.off_next;
         if (pos < nx.m && ux >= 0 && ux < nx.n && vx >= 0 && vx < nx.n) {
             store_stream(a.out + pos, i32x2{(int32_t)ux, (int32_t)vx});
-            store_stream(a.out_r + pos, e.r);
+            store_stream(a.out_r + pos, rk[k]);
             if (BID) {
                 // the next level's lightest incident edges (its min64 words
                 // were reset by this level's pointer jumping)
-                const uint64_t key = ((uint64_t)(uint32_t)e.r << 32) | (uint64_t)pos;
+                const uint64_t key = ((uint64_t)(uint32_t)rk[k] << 32) | (uint64_t)pos;
                 if (a.min64[ux] > key) atomicMin((unsigned long long*)&a.min64[ux], (unsigned long long)key);
                 if (a.min64[vx] > key) atomicMin((unsigned long long*)&a.min64[vx], (unsigned long long)key);
             }
