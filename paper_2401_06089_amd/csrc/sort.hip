@@ -128,11 +128,20 @@ __global__ __launch_bounds__(kSortBlock, sort_waves_per_eu(BITS, kSortBlock, kSo
     uint32_t key[kSortItems];
     uint32_t rank2[kSortItems / 2];
 
+    // All loads first (past the end the last element is read, then replaced
+    // by the sentinel): with the weights' key transform beside each load the
+    // compiler waited for every load before issuing the next.
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        int64_t idx = wbase + k * kWave + lane;
+        idx = idx < a.n ? idx : a.n - 1;
+        key[k] = SRC == SRC_WEIGHT ? __float_as_uint(load_stream(a.w + idx)) : load_stream(a.keys_in + idx);
+    }
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = wbase + k * kWave + lane;
-        key[k] = 0xffffffffu;
-        if (idx < a.n) key[k] = SRC == SRC_WEIGHT ? weight_key(load_stream(a.w + idx)) : load_stream(a.keys_in + idx);
+        if (SRC == SRC_WEIGHT) key[k] = weight_key(__uint_as_float(key[k]));
+        if (idx >= a.n) key[k] = 0xffffffffu;
     }
 
     // Stable in-wave ranking: lanes holding the same digit find each other with
