@@ -138,6 +138,7 @@ struct LevelArgs {
     int jump_steps;
     int round;
     int spread;                // k_min_incident visits edge blocks in a strided order (below)
+    uint32_t compact_guard;    // k_compact returns at once if Control::not_converged has one of these bits
 };
 
 // A forest of many small trees: the workgroups that run at once would all

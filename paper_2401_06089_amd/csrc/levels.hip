@@ -527,6 +527,9 @@ template <bool L0>
 __global__ __launch_bounds__(kScanBlock) void k_compact(LevelArgs a) {
     const LevelView L = level_view(a);
     if (L.skip || a.ctrl->err) return;
+    // Launched before the host knows whether pointer jumping has finished:
+    // then every workgroup returns here (nothing below has run yet).
+    if (a.ctrl->not_converged & a.compact_guard) return;
     const NextSizes nx = next_sizes(a);
     // the grid has at least as many threads as the next level has scan tiles
     compact_prepare(a, nx, (int64_t)blockIdx.x * kScanBlock + threadIdx.x);

@@ -244,6 +244,7 @@ struct Workspace {
     StageSlot stage[kStageSlots];
     int next_stage = 0;
     hipStream_t stream = nullptr;
+    hipEvent_t readback = nullptr; // marks a level's Control readback (the host waits for it alone)
 };
 
 std::mutex g_mu;
@@ -335,6 +336,16 @@ bool profiling(int kind) {
     return !t_capturing && (g_prof.mask & (1u << kind));
 }
 
+// Sets the algorithmic bytes of the latest timed launch of `kind`, for
+// launches enqueued before the host knew their size.
+void set_last_bytes(int kind, double bytes) {
+    for (auto it = t_pending.rbegin(); it != t_pending.rend(); ++it)
+        if (it->kind == kind) {
+            it->bytes = bytes;
+            return;
+        }
+}
+
 // Called once the stream has been synchronized.
 void drain_profile() {
     if (t_pending.empty()) return;
@@ -397,6 +408,11 @@ int ensure(Workspace& ws, size_t dev_bytes, size_t host_bytes) {
         // memset here would run on the null stream, unordered with respect to
         // non-blocking streams that may already be computing.)
     }
+    if (!ws.readback && hipEventCreateWithFlags(&ws.readback, hipEventDisableTiming) != hipSuccess) {
+        ws.readback = nullptr;
+        (void)hipGetLastError();
+        return PANDORA_ERR_HIP;
+    }
     if (ws.host_bytes < host_bytes) {
         if (ws.host) (void)hipHostFree(ws.host);
         ws.host = nullptr;
@@ -427,6 +443,7 @@ int read_ctrl(Control* dctrl, Control* hctrl, hipStream_t s, size_t bytes = kCtr
 struct Scratch {
     void* dev;
     void* host;
+    hipEvent_t readback = nullptr;   // null: wait for the whole stream at every readback
 };
 
 size_t host_bytes_for(int32_t B) { return sizeof(Control) + sizeof(int64_t) * (B + 1); }
@@ -597,20 +614,47 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             }
             PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 29.0 : 25.0) * n, launch_own(l0, a, s));
             PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 11.0 * m, launch_classify(a, s));
+            // The compaction is queued behind the first jumping round before the
+            // host waits for the readback, guarded by that round's convergence
+            // bit, so the device does not idle during the round trip; if the
+            // round left work, it returns at once and runs again after the
+            // further rounds.
+            const int kc = l0 ? PK_COMPACT : PK_COMPACT_N;
+            bool compacted = false;
             for (int round = 0;; ++round) {
                 if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
                 a.round = round;
                 PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 28.0 : 16.0) * n, launch_jump(a, s));
                 ++st.jump_launches;
-                rc = read_ctrl(ctrl, hctrl, s);
-                if (rc != PANDORA_OK) return rc;
-                if (hctrl->err) return status_from_err(hctrl->err);
+                if (round == 0 && sc.readback) {
+                    PD_TRY(hipMemcpyAsync(hctrl, ctrl, kCtrlReadback, hipMemcpyDeviceToHost, s));
+                    PD_TRY(hipEventRecord(sc.readback, s));
+                    a.compact_guard = 1u;
+                    PD_TIMED(kc, 0.0, launch_compact(a, s));
+                    PD_TRY(hipEventSynchronize(sc.readback));
+                    compacted = true;
+                } else {
+                    rc = read_ctrl(ctrl, hctrl, s);
+                    if (rc != PANDORA_OK) return rc;
+                }
+                if (hctrl->err) {
+                    PD_TRY(hipStreamSynchronize(s));
+                    return status_from_err(hctrl->err);
+                }
                 if (!(hctrl->not_converged & (1u << (round & 31)))) break;
+                compacted = false;   // the guarded compaction returned at once
             }
             const int64_t m_next = hctrl->m_next, n_next = hctrl->n_next;
-            if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m)
+            if (m_next > L.capE[j + 1] || n_next > L.capV[j + 1] || m_next >= m) {
+                PD_TRY(hipStreamSynchronize(s));
                 return PANDORA_ERR_NOT_A_TREE;
-            PD_TIMED(l0 ? PK_COMPACT : PK_COMPACT_N, 1.0 * m + 32.0 * m_next, launch_compact(a, s));
+            }
+            if (compacted) {
+                set_last_bytes(kc, 1.0 * m + 32.0 * m_next);
+            } else {
+                a.compact_guard = 0;
+                PD_TIMED(kc, 1.0 * m + 32.0 * m_next, launch_compact(a, s));
+            }
             off += n;
             n = n_next;
             m = m_next;
@@ -766,7 +810,7 @@ int run(const int64_t* voff, int32_t B, const int32_t* u, const int32_t* v, cons
     const Layout L = make_layout(N, B, tune.chain_digit_bits, tune.sort_tile_cfg);
     int rc = ensure(ws, L.total, host_bytes_for(B));
     if (rc != PANDORA_OK) return rc;
-    const Scratch sc{ws.dev, ws.host};
+    const Scratch sc{ws.dev, ws.host, ws.readback};
     // this call waits for its stream before returning, so the pinned block's
     // staging area is free again by the next call
     int64_t* hv = reinterpret_cast<int64_t*>(static_cast<char*>(ws.host) + sizeof(Control));
@@ -1013,7 +1057,7 @@ int run_flat(int64_t n, const int32_t* u, const int32_t* v, const float* w, int3
     const FlatLayout FL = make_flat_layout(N, mcs);
     int rc = ensure(ws, L.total + FL.total, host_bytes_for(1));
     if (rc != PANDORA_OK) return rc;
-    const Scratch sc{ws.dev, ws.host};
+    const Scratch sc{ws.dev, ws.host, ws.readback};
     int64_t* hv = reinterpret_cast<int64_t*>(static_cast<char*>(ws.host) + sizeof(Control));
     hv[0] = 0;
     hv[1] = N;
@@ -1788,6 +1832,8 @@ void pandora_release_workspaces(void) {
         if (ws.dev && ws.owned) (void)hipFree(ws.dev);
         if (ws.host) (void)hipHostFree(ws.host);
         if (ws.sticky) (void)hipFree(ws.sticky);
+        if (ws.readback) (void)hipEventDestroy(ws.readback);
+        ws.readback = nullptr;
         for (StageSlot& sl : ws.stage) {
             if (sl.host) (void)hipHostFree(sl.host);
             if (sl.done) (void)hipEventDestroy(sl.done);
