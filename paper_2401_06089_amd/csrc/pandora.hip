@@ -613,7 +613,9 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
                 break;
             }
             PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 29.0 : 25.0) * n, launch_own(l0, a, s));
-            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 11.0 * m, launch_classify(a, s));
+            // classification and the first jumping round: bytes set once the
+            // next level's size is read back (below)
+            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 3.0 * m, launch_classify(a, s));
             // The compaction is queued behind the first jumping round before the
             // host waits for the readback, guarded by that round's convergence
             // bit, so the device does not idle during the round trip; if the
@@ -624,7 +626,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
             for (int round = 0;; ++round) {
                 if (round >= kMaxJumpRounds) return PANDORA_ERR_NOT_A_TREE;
                 a.round = round;
-                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 28.0 : 16.0) * n, launch_jump(a, s));
+                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 18.0 : 4.0) * n, launch_jump(a, s));
                 ++st.jump_launches;
                 if (round == 0 && sc.readback) {
                     PD_TRY(hipMemcpyAsync(hctrl, ctrl, kCtrlReadback, hipMemcpyDeviceToHost, s));
@@ -640,6 +642,13 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
                 if (hctrl->err) {
                     PD_TRY(hipStreamSynchronize(s));
                     return status_from_err(hctrl->err);
+                }
+                if (round == 0) {
+                    // n_next leaf edges: their endpoints are labelled by the
+                    // classification, which reads only those edges' records
+                    const double nn = (double)hctrl->n_next;
+                    set_last_bytes(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 3.0 * m + 16.0 * nn);
+                    set_last_bytes(l0 ? PK_JUMP : PK_JUMP_N, 24.0 * n - 12.0 * nn);
                 }
                 if (!(hctrl->not_converged & (1u << (round & 31)))) break;
                 compacted = false;   // the guarded compaction returned at once
@@ -684,11 +693,11 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
                 break;
             }
             PD_TIMED(l0 ? PK_OWN : PK_OWN_N, (l0 ? 29.0 : 25.0) * nj, launch_own(l0, a, s));
-            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 11.0 * mj, launch_classify(a, s));
+            PD_TIMED(l0 ? PK_CLASSIFY : PK_CLASSIFY_N, 3.0 * mj, launch_classify(a, s));
             for (int round = 0; round < kSyncFreeJumpRounds; ++round) {
                 a.round = round;
                 a.jump_steps = round + 1 < kSyncFreeJumpRounds ? jump_steps : (int)std::max<int64_t>(L.capV[j], 16);
-                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, (round == 0 ? 28.0 : 16.0) * nj, launch_jump(a, s));
+                PD_TIMED(l0 ? PK_JUMP : PK_JUMP_N, round == 0 ? 18.0 * nj : 0.0, launch_jump(a, s));
                 ++st.jump_launches;
             }
             // sizes are capacities here; about a third of a level's edges are alpha
@@ -732,7 +741,7 @@ int enqueue(const Scratch& sc, const Layout& L, const pandora_tuning_t& tune, bo
         const int64_t lbw_c = sort_tiles(M, L.sort_cfg) << chain.widest();
         wa.lb_zero_words = lbw_c;
         wa.ctrl = ctrl;
-        PD_TIMED(PK_WALK_HIST, 16.0 * M, launch_walk_hist(wa, s));
+        PD_TIMED(PK_WALK_HIST, 8.0 * M, launch_walk_hist(wa, s));   // lookups added once counted
         const uint32_t* kin = K[0];
         const int32_t* vin = perm;
         st.chain_passes = chain.passes;
@@ -787,6 +796,12 @@ int finish(const Scratch& sc, const Layout& L, int32_t B, hipStream_t s, Stats& 
     st.sum_edges += hctrl->lv[entry].m;
     st.tail_levels = hctrl->tail_levels;
     st.levels = entry + hctrl->tail_levels;
+    // The walk looks up a record for every edge but the leaf edges, one per
+    // vertex above level 0 (those of the levels up to the tail's entry are
+    // known here; the tail's few further ones are counted as lookups).
+    int64_t leaf = 0;
+    for (int j = 1; j <= entry; ++j) leaf += hctrl->lv[j].n;
+    set_last_bytes(PK_WALK_HIST, 8.0 * (double)L.M + 8.0 * (double)std::max<int64_t>(0, L.M - leaf));
     return PANDORA_OK;
 }
 
