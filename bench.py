@@ -21,6 +21,7 @@ run.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -784,6 +785,13 @@ def run_serving(args, dev, emit=True):
                 done_cv.notify_all()
         return cb
 
+    # Python's cyclic garbage collector is paused for the timed window: its
+    # full collections walk every live request record the client keeps for
+    # the statistics (10^5 of them) and stall every thread, the server's
+    # workers included, for tens of milliseconds.  Reference counting still
+    # frees every result as soon as the client drops it.
+    gc_was_enabled = gc.isenabled()
+    gc.disable()
     start = time.perf_counter()
     reqs = []
     for i, off in enumerate(offsets):
@@ -800,6 +808,8 @@ def run_serving(args, dev, emit=True):
         while done["n"] < len(reqs):
             done_cv.wait(timeout=1.0)
     end = time.perf_counter()
+    if gc_was_enabled:
+        gc.enable()
     if done["failed"]:
         raise RuntimeError(f"{len(done['failed'])} requests failed, first: {done['failed'][0]}")
     srv.close()
