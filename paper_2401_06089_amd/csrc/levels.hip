@@ -9,9 +9,10 @@
 // One level, m_j edges and n_j vertices:
 //   k_min_incident  min64[x] = min over incident edges of (rank << 32 | pos):
 //                   the lightest incident edge (Eq. vertexparent) and where
-//                   its record lives.  At level 0 it also builds the 16-byte
-//                   edge records from the caller's arrays, translating the
-//                   tree-local ids of a forest and validating them.
+//                   its record lives.  At level 0 it also builds the 8-byte
+//                   (u, v) edge records from the caller's arrays (ranks stay in
+//                   their own array), translating the tree-local ids of a
+//                   forest and validating them.
 //   k_own           per vertex: one gather of its lightest edge's record gives
 //                   the hook ptr[x] = other endpoint, the rank table entry and
 //                   (level 0) the vertex's dendrogram parent; the vertex marks
@@ -21,8 +22,9 @@
 //                   hooks except across a leaf edge, so every supervertex is one
 //                   pointer tree whose root is its leaf edge's smaller endpoint.
 //                   A decoupled look-back scan of leaf flags (alpha count
-//                   alongside) numbers the next level's vertices; each root's
-//                   ptr word receives its label with the flag bit set.
+//                   alongside) numbers the next level's vertices; both
+//                   endpoints of each leaf edge receive its label in their ptr
+//                   words with the flag bit set.
 //   k_jump          pointer jumping in place (bounded steps per launch; the
 //                   host relaunches until every vertex has its label); each
 //                   vertex writes its flat label and records its lightest
